@@ -1,0 +1,205 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) library for the pseudopotential
+ * multiphase lattice Boltzmann step with contact angles on curved walls
+ * (Li, Yu & Luo, "Implementation of contact angles in the pseudopotential
+ * lattice Boltzmann simulations with curved boundaries").
+ *
+ * One time step (Sec. II A, Sec. III B, Sec. IV A):
+ *   rho = sum_a f_a (Eq. 4) -> psi(rho) from the equation of state (Eq. 6)
+ *   -> virtual density of the solid nodes next to the fluid: the improved
+ *      local scheme (Eqs. 16-17 with the limiter rho_g <= rho_w <= rho_l),
+ *      the constant virtual density, or no pseudopotential in the solid for
+ *      the solid-fluid interaction (Eq. 8)
+ *   -> force F = F_m (Eq. 5) [+ F_ads (Eq. 8)] [+ body force]
+ *   -> u (Eq. 4) -> MRT collision in moment space with the forcing of Eq. 7
+ *      (Eq. 2) -> streaming (Eq. 3) with halfway bounce-back at the
+ *      staircase wall (Fig. 3).
+ *
+ * Conventions
+ *  - Lattice units: dx = dt = 1, c = 1, cs^2 = 1/3.
+ *  - Node index n = x + nx*(y + ny*z), x fastest; every axis is periodic.
+ *    Walls (cylinders, spheres, plates) are solid nodes.
+ *  - Populations are structure-of-arrays f[a*N + n] (N = nx*ny*nz) in the
+ *    velocity order: D2Q9 rest, +x, +y, -x, -y, (1,1), (-1,1), (-1,-1),
+ *    (1,-1); D3Q19 rest, +x, -x, +y, -y, +z, -z, (1,1,0), (-1,-1,0),
+ *    (1,-1,0), (-1,1,0), (1,0,1), (-1,0,-1), (1,0,-1), (-1,0,1), (0,1,1),
+ *    (0,-1,-1), (0,1,-1), (0,-1,1).  The state is the post-streaming
+ *    population set at integer time t.
+ *  - Real-valued device arrays are in the context precision (float for
+ *    precision 4, double for precision 8).
+ *  - "dev" pointers are device memory; "host" pointers are host memory.
+ *    Device pointers passed in are borrowed for the duration of the call
+ *    only (reads and writes are ordered on the context stream).
+ *  - Every call returns LBM_OK (0) or a negative error code; no C++
+ *    exception crosses this interface.  lbm_last_error() gives a
+ *    thread-local message for the last failure.
+ *  - The library never allocates device memory: all device storage lives
+ *    in the caller-owned workspace given to lbm_create/lbm_create_batch.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,  /* invalid argument or parameter */
+    LBM_ENOMEM = -2,  /* workspace too small */
+    LBM_EDOMAIN = -3, /* psi argument negative or NaN (Eq. 6 undefined) */
+    LBM_ESTATE = -4,  /* call out of order (e.g. step before geometry) */
+    LBM_EDEVICE = -5  /* HIP runtime error */
+};
+
+enum { LBM_EOS_CS = 0, LBM_EOS_PR = 1 };
+enum { LBM_WET_IVD = 0, LBM_WET_VD = 1, LBM_WET_SFI = 2 };
+
+/* Model parameters, copied at create.
+ *  lattice     9 (D2Q9) or 19 (D3Q19)
+ *  precision   4 (float) or 8 (double)
+ *  nx, ny, nz  lattice size (nz = 1 for D2Q9)
+ *  tau[k]      relaxation time of moment row k (Eq. 2); all > 0.5.  Row
+ *              order is that of the relaxation matrix of Eq. 2: D2Q9
+ *              (rho, e, eps, jx, qx, jy, qy, pxx, pxy); D3Q19 (rho, e, eps,
+ *              jx, qx, jy, qy, jz, qz, 3pxx, 3pixx, pww, piww, pxy, pyz,
+ *              pxz, mx, my, mz).  nu = (tau_nu - 0.5)/3.
+ *  eos         LBM_EOS_CS: p = rho R T (1+h+h^2-h^3)/(1-h)^3 - a rho^2,
+ *              h = b rho / 4 (Carnahan-Starling).  LBM_EOS_PR: Eq. 18 with
+ *              acentric factor eos_omega and Tc = (0.0778/0.45724)(a/b)/R.
+ *  eos_T       absolute temperature
+ *  G           interaction strength of Eqs. 5-6 (the paper uses -1)
+ *  sigma       thermodynamic-consistency constant of Eq. 7
+ *  body_force  constant force density added to F (e.g. Poiseuille drive)
+ *  rho_g,rho_l limiter bounds of the improved virtual density (Sec. III B):
+ *              the coexisting gas and liquid densities. rho_g < rho_l. */
+typedef struct {
+    int32_t lattice;
+    int32_t precision;
+    int32_t nx, ny, nz;
+    int32_t eos;
+    double tau[19];
+    double eos_a, eos_b, eos_R, eos_T, eos_omega;
+    double G;
+    double sigma;
+    double body_force[3];
+    double rho_g, rho_l;
+} lbm_params;
+
+/* Diagnostics of the current state (reductions over the fluid nodes). */
+typedef struct {
+    double mass;    /* sum of rho over fluid nodes (accumulated in double) */
+    double max_u;   /* max |u| over fluid nodes (spurious currents) */
+    double rho_min; /* min rho over fluid nodes */
+    double rho_max; /* max rho over fluid nodes */
+    int32_t flag;   /* nonzero: a step met a psi argument < 0 or NaN */
+    int32_t n_fluid;
+} lbm_diag;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* ---------------------------------------------------------------- status */
+const char* lbm_version(void);
+const char* lbm_status_string(int code);
+/* Message for the last failing call on this thread ("" if none). */
+const char* lbm_last_error(void);
+
+/* Host-only check of a parameter set (no device needed).  Returns
+ * LBM_EINVAL with a message for: lattice not 9/19, precision not 4/8, a
+ * non-positive size, nz != 1 for D2Q9, tau <= 0.5, non-positive EOS
+ * constants, rho_g >= rho_l or rho_g <= 0. */
+int lbm_validate_params(const lbm_params* p);
+
+/* ------------------------------------------------------- thermodynamics */
+/* Host helpers for the equation of state (Eq. 6, Eq. 18).  Critical point
+ * (Tc and the density there); for PR, Tc follows from a, b, R. */
+int lbm_eos_critical(int32_t eos, double a, double b, double R, double omega,
+                     double* Tc, double* rhoc);
+/* Maxwell equal-area coexistence densities at p->eos_T (< Tc). */
+int lbm_eos_coexistence(const lbm_params* p, double* rho_g, double* rho_l);
+/* Pressure of the EOS and the psi of Eq. 6 at one density (host). */
+int lbm_eos_eval(const lbm_params* p, double rho, double* p_eos, double* psi);
+
+/* ------------------------------------------------------------ lifetime */
+/* Bytes of device workspace a context of these parameters needs, with room
+ * for up to n_wall_max wall nodes (solid nodes adjacent to fluid).  0 if
+ * the parameters are invalid. */
+size_t lbm_workspace_bytes(const lbm_params* p, int64_t n_wall_max);
+
+/* Create a context.  stream: a hipStream_t (NULL = default stream) on which
+ * every launch and copy of this context is ordered.  workspace: device
+ * memory of ws_bytes >= lbm_workspace_bytes(p, n_wall_max), owned by the
+ * caller and kept alive (and not touched) until lbm_destroy.  Errors:
+ * LBM_EINVAL (parameters), LBM_ENOMEM (workspace too small),
+ * LBM_EDEVICE. */
+int lbm_create(const lbm_params* p, void* stream, void* workspace,
+               size_t ws_bytes, int64_t n_wall_max, lbm_ctx** out);
+/* Free the host-side context (the workspace stays the caller's). */
+int lbm_destroy(lbm_ctx* ctx);
+
+/* ------------------------------------------------------------- problem */
+/* Solid geometry (Sec. IV, Fig. 3): solid_host[n] = 1 for solid, 0 for
+ * fluid, N bytes of host memory, read during the call.  Builds the node
+ * classes and the list of wall nodes (solid nodes with a fluid neighbour in
+ * the Eq. 5 stencil, increasing n) and uploads them; blocks until the
+ * upload is done.  Resets wetting to the improved scheme with phi = 1,
+ * drho = 0 and marks the fields unset.  Errors: LBM_EINVAL (more than
+ * n_wall_max wall nodes, or no fluid node). */
+int lbm_set_geometry(lbm_ctx* ctx, const uint8_t* solid_host);
+
+/* Number of wall nodes and (if idx_host != NULL) their node indices in the
+ * order used by the per-wall-node arrays of lbm_set_wetting/lbm_adjoint. */
+int lbm_wall_nodes(lbm_ctx* ctx, int64_t* idx_host, int64_t* count);
+
+/* Contact-angle scheme.
+ *  LBM_WET_IVD  improved virtual density (Eqs. 16-17): per wall node b,
+ *               rho_w = clamp(phi_b * rho_ave - drho_b, rho_g, rho_l), with
+ *               rho_ave the w-weighted mean density of the fluid neighbours.
+ *               phi_dev/drho_dev: device arrays of count wall entries in the
+ *               context precision, or NULL for the uniform phi0/drho0.
+ *  LBM_WET_VD   constant virtual density rho_w = scalar on every wall node.
+ *  LBM_WET_SFI  solid-fluid interaction (Eq. 8) with G_w = scalar; the
+ *               solid carries psi = 0.
+ * Errors: LBM_ESTATE (no geometry), LBM_EINVAL (unknown scheme, phi <= 0,
+ * VD density outside the range where Eq. 6 is real). */
+int lbm_set_wetting(lbm_ctx* ctx, int32_t scheme, double scalar,
+                    const void* phi_dev, const void* drho_dev, double phi0,
+                    double drho0);
+
+/* Initial state f = f_eq(rho, u) on fluid nodes (0 on solid).  rho_dev: N
+ * reals; u_dev: D*N reals ([D][N]) or NULL for rest.  Errors: LBM_ESTATE
+ * (no geometry). */
+int lbm_set_fields(lbm_ctx* ctx, const void* rho_dev, const void* u_dev);
+/* Raw state: f_dev holds Q*N reals ([Q][N]), copied in (checkpoint
+ * restore).  Values on solid nodes are ignored. */
+int lbm_set_state(lbm_ctx* ctx, const void* f_dev);
+
+/* --------------------------------------------------------------- steps */
+/* Advance nsteps >= 0 time steps, asynchronously on the context stream.
+ * Errors: LBM_ESTATE (geometry or fields unset), LBM_EDOMAIN if a previous
+ * diagnostics call found the domain flag set (sticky until new fields). */
+int lbm_step(lbm_ctx* ctx, int64_t nsteps);
+
+/* Macroscopic fields of the current state, written stream-ordered to
+ * caller device arrays (each may be NULL): rho_dev N reals (fluid: density;
+ * wall nodes: their virtual density, 0 under SFI; other solid: 0), u_dev
+ * D*N reals ([D][N], 0 on solid), f_dev Q*N reals (the state). */
+int lbm_get_fields(lbm_ctx* ctx, void* rho_dev, void* u_dev, void* f_dev);
+
+/* Reductions over the current state; synchronises the context stream.
+ * Returns LBM_EDOMAIN (and sets the sticky error) if the device domain flag
+ * is set. */
+int lbm_get_diagnostics(lbm_ctx* ctx, lbm_diag* host_out);
+
+/* lbm_step followed by a host wait, timed with HIP events recorded on the
+ * context stream right before the first and after the last step launch;
+ * ms_total receives the elapsed time of the nsteps launches. */
+int lbm_step_timed(lbm_ctx* ctx, int64_t nsteps, double* ms_total);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

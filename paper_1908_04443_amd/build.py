@@ -1,0 +1,79 @@
+"""Build the gfx950 library paper_1908_04443_amd/liblbm.so in-tree.
+
+Every source under csrc/ is compiled by hipcc for gfx950 (device code) and
+the host objects are linked with g++ against the HIP runtime that PyTorch
+ships, so that one process holds a single HIP runtime when the library is
+used next to torch.  Packed-FP32 code generation is disabled (see the
+compile flags), FMA contraction is off so that the FP64 build follows the
+same rounding steps as a plain scalar evaluation.
+"""
+import os
+import subprocess
+import sys
+import sysconfig
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "liblbm.so")
+BUILD = os.path.join(HERE, "_build")
+
+SOURCES = ["api.cpp", "thermo.cpp", "geometry.cpp", "step2d.hip", "step_march.hip",
+           "aux.hip"]
+EXTRA_SOURCES = []
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ARCH = "gfx950"
+
+COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall",
+          "-Wno-unused-variable", "-Wno-unused-function"]
+DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
+          "-packed-fp32-ops", "-munsafe-fp-atomics"]
+
+
+def torch_lib_dir():
+    # locate torch's lib dir without importing torch (keeps the build fast)
+    for base in (sysconfig.get_paths()["purelib"], sysconfig.get_paths()["platlib"]):
+        d = os.path.join(base, "torch", "lib")
+        if os.path.exists(os.path.join(d, "libamdhip64.so")):
+            return d
+    import torch  # fallback
+    return os.path.join(os.path.dirname(torch.__file__), "lib")
+
+
+def _run(cmd, verbose):
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+
+
+def build(verbose=False, jobs=8):
+    os.makedirs(BUILD, exist_ok=True)
+    objs, procs = [], []
+    for src in SOURCES + EXTRA_SOURCES:
+        path = os.path.join(CSRC, src)
+        obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+        if src.endswith(".hip"):
+            cmd = [HIPCC, *COMMON, *DEVICE, "-x", "hip", "-c", path, "-o", obj]
+        else:
+            cmd = [HIPCC, *COMMON, "-c", path, "-o", obj]
+        objs.append(obj)
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((subprocess.Popen(cmd), src))
+        if len(procs) >= jobs:
+            p, s = procs.pop(0)
+            if p.wait() != 0:
+                raise RuntimeError(f"compile failed: {s}")
+    for p, s in procs:
+        if p.wait() != 0:
+            raise RuntimeError(f"compile failed: {s}")
+    tlib = torch_lib_dir()
+    tmp = LIB + ".tmp"
+    _run(["g++", "-shared", "-o", tmp, *objs, f"-L{tlib}", "-lamdhip64",
+          f"-Wl,-rpath,{tlib}", "-Wl,--no-undefined", "-Wl,--disable-new-dtags"], verbose)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv))

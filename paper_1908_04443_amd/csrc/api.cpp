@@ -1,0 +1,443 @@
+// api.cpp -- the extern "C" entry points of include/lbm.h.
+//
+// Host code only: argument and call-order validation, workspace carving,
+// geometry upload and stream-ordered kernel launches.  No device memory is
+// allocated here; every device array is carved from the caller's workspace.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "lbm_host.hpp"
+
+namespace lbm {
+
+static thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+int ok() { return LBM_OK; }
+
+int validate(const lbm_params* p) {
+    if (!p) return fail(LBM_EINVAL, "params is NULL");
+    if (p->lattice != 9 && p->lattice != 19) return fail(LBM_EINVAL, "lattice must be 9 or 19");
+    if (p->precision != 4 && p->precision != 8) return fail(LBM_EINVAL, "precision must be 4 or 8");
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail(LBM_EINVAL, "sizes must be positive");
+    if (p->lattice == 9 && p->nz != 1) return fail(LBM_EINVAL, "D2Q9 needs nz == 1");
+    const double N = (double)p->nx * p->ny * p->nz;
+    if (N > 4.0e9) return fail(LBM_EINVAL, "lattice too large");
+    for (int k = 0; k < p->lattice; ++k)
+        if (!(p->tau[k] > 0.5)) return fail(LBM_EINVAL, "every tau must exceed 0.5");
+    if (p->eos != LBM_EOS_CS && p->eos != LBM_EOS_PR) return fail(LBM_EINVAL, "unknown eos");
+    if (!(p->eos_a > 0 && p->eos_b > 0 && p->eos_R > 0 && p->eos_T > 0))
+        return fail(LBM_EINVAL, "EOS constants must be positive");
+    if (!(p->G != 0.0) || !std::isfinite(p->G)) return fail(LBM_EINVAL, "G must be nonzero");
+    if (!std::isfinite(p->sigma)) return fail(LBM_EINVAL, "sigma must be finite");
+    if (!(p->rho_g > 0 && p->rho_g < p->rho_l)) return fail(LBM_EINVAL, "need 0 < rho_g < rho_l");
+    return LBM_OK;
+}
+
+template <typename real>
+static Coef<real> make_coef(const lbm_ctx* c) {
+    const lbm_params& p = c->p;
+    Coef<real> C;
+    std::memset(&C, 0, sizeof C);
+    C.nx = p.nx;
+    C.ny = p.ny;
+    C.nz = p.nz;
+    C.scheme = c->scheme;
+    C.eos = p.eos;
+    C.eos_a = (real)p.eos_a;
+    C.eos_b = (real)p.eos_b;
+    C.eos_RT = (real)(p.eos_R * p.eos_T);
+    C.eos_aphi = (real)(p.eos == LBM_EOS_PR ? pr_aphi(p) : 0.0);
+    C.two_over_G = (real)(2.0 / p.G);
+    C.G = (real)p.G;
+    if (c->scheme == LBM_WET_VD) {
+        C.rho_w = (real)c->scalar;
+        C.psi_w = (real)std::sqrt(psi_argument(p, c->scalar));
+    }
+    if (c->scheme == LBM_WET_SFI) C.G_w = (real)c->scalar;
+    C.rho_g = (real)p.rho_g;
+    C.rho_l = (real)p.rho_l;
+    for (int k = 0; k < 19; ++k) {
+        const double s = (k < p.lattice) ? 1.0 / p.tau[k] : 1.0;
+        C.s[k] = (real)s;
+        C.hs[k] = (real)(1.0 - 0.5 * s);
+    }
+    if (p.lattice == 9) {
+        C.sig_e = (real)(12.0 * p.sigma / (p.tau[1] - 0.5));
+        C.sig_eps = (real)(12.0 * p.sigma / (p.tau[2] - 0.5));
+    } else {
+        C.sig_e = (real)(114.0 * p.sigma / (p.tau[1] - 0.5));
+        C.sig_eps = (real)0;
+    }
+    for (int d = 0; d < 3; ++d) C.body[d] = (real)p.body_force[d];
+    return C;
+}
+
+template <typename real>
+static Fields<real> make_fields(const lbm_ctx* c, int src) {
+    Fields<real> F;
+    F.fin = (const real*)c->f[src];
+    F.fout = (real*)c->f[src ^ 1];
+    F.cls = c->cls;
+    F.widx = c->widx;
+    F.phi = (const real*)c->phi;
+    F.drho = (const real*)c->drho;
+    F.flag = c->flag;
+    return F;
+}
+
+static int grid_blocks(const lbm_params& p) {
+    if (p.lattice == 9)
+        return p.precision == 4 ? grid2d_blocks<float>(p.nx, p.ny) : grid2d_blocks<double>(p.nx, p.ny);
+    return p.precision == 4 ? grid3d_blocks<float>(p.nx, p.ny, p.nz)
+                            : grid3d_blocks<double>(p.nx, p.ny, p.nz);
+}
+
+// lay out the workspace; with ctx == nullptr only the size is computed
+static size_t layout(const lbm_params& p, int64_t nwm, lbm_ctx* c) {
+    Carver cv(c ? c->ws : nullptr, c ? c->ws_bytes : 0);
+    const int64_t N = (int64_t)p.nx * p.ny * p.nz;
+    const size_t s = (size_t)p.precision;
+    const int Q = p.lattice;
+    const int64_t nw = nwm > 0 ? nwm : 1;
+    const int nparts = grid_blocks(p);
+    void* f0 = cv.take<char>((size_t)Q * N * s);
+    void* f1 = cv.take<char>((size_t)Q * N * s);
+    uint8_t* cls = cv.take<uint8_t>(N);
+    int32_t* widx = cv.take<int32_t>(N);
+    int32_t* wl = cv.take<int32_t>(nw);
+    void* phi = cv.take<char>(nw * s);
+    void* drho = cv.take<char>(nw * s);
+    int32_t* flag = cv.take<int32_t>(4);
+    double* part = cv.take<double>(5 * (size_t)nparts);
+    double* dout = cv.take<double>(8);
+    if (c) {
+        c->f[0] = f0;
+        c->f[1] = f1;
+        c->cls = cls;
+        c->widx = widx;
+        c->wall_list = wl;
+        c->phi = phi;
+        c->drho = drho;
+        c->flag = flag;
+        c->part = part;
+        c->diag_out = dout;
+        c->nparts = nparts;
+    }
+    return (cv.off + 255) & ~size_t(255);
+}
+
+template <typename real>
+static int launch_mode(lbm_ctx* c, int mode, real* rho, real* u, double* part) {
+    Coef<real> C = make_coef<real>(c);
+    Fields<real> F = make_fields<real>(c, c->cur);
+    FieldOut<real> O{rho, u, part};
+    hipError_t e = (c->p.lattice == 9) ? launch_step2d<real>(C, F, O, mode, c->stream)
+                                       : launch_step3d<real>(C, F, O, mode, c->stream);
+    if (e != hipSuccess) return fail(LBM_EDEVICE, std::string("step launch: ") + hipGetErrorString(e));
+    return LBM_OK;
+}
+
+template <typename real>
+static int run_steps(lbm_ctx* c, int64_t nsteps) {
+    Coef<real> C = make_coef<real>(c);
+    FieldOut<real> O{nullptr, nullptr, nullptr};
+    for (int64_t i = 0; i < nsteps; ++i) {
+        Fields<real> F = make_fields<real>(c, c->cur);
+        hipError_t e = (c->p.lattice == 9) ? launch_step2d<real>(C, F, O, MODE_STEP, c->stream)
+                                           : launch_step3d<real>(C, F, O, MODE_STEP, c->stream);
+        if (e != hipSuccess)
+            return fail(LBM_EDEVICE, std::string("step launch: ") + hipGetErrorString(e));
+        c->cur ^= 1;
+    }
+    return LBM_OK;
+}
+
+template <typename real>
+static int fill_wetting(lbm_ctx* c, const void* phi_dev, const void* drho_dev, double phi0,
+                        double drho0) {
+    const int64_t nw = (int64_t)c->geom.walls.size();
+    const size_t bytes = (size_t)nw * sizeof(real);
+    if (nw == 0) return LBM_OK;
+    if (phi_dev)
+        LBM_HIP(hipMemcpyAsync(c->phi, phi_dev, bytes, hipMemcpyDeviceToDevice, c->stream));
+    else
+        LBM_HIP(launch_fill<real>((real*)c->phi, (real)phi0, nw, c->stream));
+    if (drho_dev)
+        LBM_HIP(hipMemcpyAsync(c->drho, drho_dev, bytes, hipMemcpyDeviceToDevice, c->stream));
+    else
+        LBM_HIP(launch_fill<real>((real*)c->drho, (real)drho0, nw, c->stream));
+    if (phi_dev) {
+        std::vector<real> h(nw);
+        LBM_HIP(hipMemcpyAsync(h.data(), c->phi, bytes, hipMemcpyDeviceToHost, c->stream));
+        LBM_HIP(hipStreamSynchronize(c->stream));
+        for (int64_t i = 0; i < nw; ++i)
+            if (!(h[i] > 0)) return fail(LBM_EINVAL, "phi must be positive on every wall node");
+    }
+    return LBM_OK;
+}
+
+}  // namespace lbm
+
+using namespace lbm;
+
+extern "C" {
+
+const char* lbm_version(void) { return "lbm-gfx950 1.0"; }
+
+const char* lbm_status_string(int code) {
+    switch (code) {
+    case LBM_OK: return "ok";
+    case LBM_EINVAL: return "invalid argument";
+    case LBM_ENOMEM: return "workspace too small";
+    case LBM_EDOMAIN: return "psi argument negative or NaN";
+    case LBM_ESTATE: return "call out of order";
+    case LBM_EDEVICE: return "HIP runtime error";
+    default: return "unknown status";
+    }
+}
+
+const char* lbm_last_error(void) { return g_err.c_str(); }
+
+int lbm_validate_params(const lbm_params* p) { return validate(p); }
+
+int lbm_eos_critical(int32_t eos, double a, double b, double R, double omega, double* Tc,
+                     double* rhoc) {
+    if (eos != LBM_EOS_CS && eos != LBM_EOS_PR) return fail(LBM_EINVAL, "unknown eos");
+    if (!(a > 0 && b > 0 && R > 0)) return fail(LBM_EINVAL, "EOS constants must be positive");
+    int rc = eos_critical(eos, a, b, R, omega, Tc, rhoc);
+    return rc == LBM_OK ? rc : fail(rc, "critical point not bracketed");
+}
+
+int lbm_eos_coexistence(const lbm_params* p, double* rho_g, double* rho_l) {
+    if (!p || !rho_g || !rho_l) return fail(LBM_EINVAL, "NULL argument");
+    if (!(p->eos_a > 0 && p->eos_b > 0 && p->eos_R > 0 && p->eos_T > 0))
+        return fail(LBM_EINVAL, "EOS constants must be positive");
+    int rc = eos_coexistence(*p, rho_g, rho_l);
+    return rc == LBM_OK ? rc : fail(rc, "temperature is not below the critical point");
+}
+
+int lbm_eos_eval(const lbm_params* p, double rho, double* p_eos, double* psi) {
+    if (!p) return fail(LBM_EINVAL, "NULL params");
+    const double pe = eos_pressure(*p, rho);
+    const double arg = psi_argument(*p, rho);
+    if (p_eos) *p_eos = pe;
+    if (psi) *psi = arg >= 0 ? std::sqrt(arg) : std::nan("");
+    return arg >= 0 ? LBM_OK : fail(LBM_EDOMAIN, "psi argument negative");
+}
+
+size_t lbm_workspace_bytes(const lbm_params* p, int64_t n_wall_max) {
+    if (validate(p) != LBM_OK || n_wall_max < 0) return 0;
+    return layout(*p, n_wall_max, nullptr);
+}
+
+int lbm_create(const lbm_params* p, void* stream, void* workspace, size_t ws_bytes,
+               int64_t n_wall_max, lbm_ctx** out) {
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate(p);
+    if (rc != LBM_OK) return rc;
+    if (n_wall_max < 0) return fail(LBM_EINVAL, "n_wall_max must be >= 0");
+    const size_t need = layout(*p, n_wall_max, nullptr);
+    if (!workspace || ws_bytes < need)
+        return fail(LBM_ENOMEM, "workspace needs " + std::to_string(need) + " bytes");
+    if (((uintptr_t)workspace & 255) != 0) return fail(LBM_EINVAL, "workspace must be 256-byte aligned");
+    lbm_ctx* c = new (std::nothrow) lbm_ctx();
+    if (!c) return fail(LBM_EINVAL, "host allocation failed");
+    c->p = *p;
+    c->Q = p->lattice;
+    c->D = p->lattice == 9 ? 2 : 3;
+    c->N = (int64_t)p->nx * p->ny * p->nz;
+    c->prec = p->precision;
+    c->stream = (hipStream_t)stream;
+    c->ws = workspace;
+    c->ws_bytes = ws_bytes;
+    c->n_wall_max = n_wall_max;
+    layout(*p, n_wall_max, c);
+    if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+        delete c;
+        return fail(LBM_EDEVICE, "hipEventCreate failed");
+    }
+    *out = c;
+    return LBM_OK;
+}
+
+int lbm_destroy(lbm_ctx* c) {
+    if (!c) return LBM_OK;
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    delete c;
+    return LBM_OK;
+}
+
+int lbm_set_geometry(lbm_ctx* c, const uint8_t* solid_host) {
+    if (!c || !solid_host) return fail(LBM_EINVAL, "NULL argument");
+    Geometry g;
+    build_geometry(c->p, solid_host, g);
+    if ((int64_t)g.walls.size() > c->n_wall_max)
+        return fail(LBM_EINVAL, "geometry has " + std::to_string(g.walls.size()) +
+                                    " wall nodes, more than n_wall_max = " +
+                                    std::to_string(c->n_wall_max));
+    if (g.n_fluid == 0) return fail(LBM_EINVAL, "geometry has no fluid node");
+    std::vector<int32_t> wl(g.walls.size());
+    for (size_t i = 0; i < wl.size(); ++i) wl[i] = (int32_t)g.walls[i];
+    LBM_HIP(hipMemcpyAsync(c->cls, g.cls.data(), (size_t)c->N, hipMemcpyHostToDevice, c->stream));
+    LBM_HIP(hipMemcpyAsync(c->widx, g.widx.data(), (size_t)c->N * 4, hipMemcpyHostToDevice,
+                           c->stream));
+    if (!wl.empty())
+        LBM_HIP(hipMemcpyAsync(c->wall_list, wl.data(), wl.size() * 4, hipMemcpyHostToDevice,
+                               c->stream));
+    LBM_HIP(hipStreamSynchronize(c->stream));
+    c->geom = std::move(g);
+    c->have_geom = true;
+    c->have_fields = false;
+    c->scheme = LBM_WET_IVD;
+    c->scalar = 0.0;
+    int rc = (c->prec == 4) ? fill_wetting<float>(c, nullptr, nullptr, 1.0, 0.0)
+                            : fill_wetting<double>(c, nullptr, nullptr, 1.0, 0.0);
+    if (rc != LBM_OK) return rc;
+    LBM_HIP(launch_fill_i32(c->flag, 0, 4, c->stream));
+    return LBM_OK;
+}
+
+int lbm_wall_nodes(lbm_ctx* c, int64_t* idx_host, int64_t* count) {
+    if (!c || !count) return fail(LBM_EINVAL, "NULL argument");
+    if (!c->have_geom) return fail(LBM_ESTATE, "no geometry set");
+    *count = (int64_t)c->geom.walls.size();
+    if (idx_host)
+        for (size_t i = 0; i < c->geom.walls.size(); ++i) idx_host[i] = c->geom.walls[i];
+    return LBM_OK;
+}
+
+int lbm_set_wetting(lbm_ctx* c, int32_t scheme, double scalar, const void* phi_dev,
+                    const void* drho_dev, double phi0, double drho0) {
+    if (!c) return fail(LBM_EINVAL, "NULL context");
+    if (!c->have_geom) return fail(LBM_ESTATE, "set the geometry before the wetting scheme");
+    if (scheme == LBM_WET_IVD) {
+        if (!phi_dev && !(phi0 > 0)) return fail(LBM_EINVAL, "phi must be positive");
+        if (!std::isfinite(drho0)) return fail(LBM_EINVAL, "drho must be finite");
+        int rc = (c->prec == 4) ? fill_wetting<float>(c, phi_dev, drho_dev, phi0, drho0)
+                                : fill_wetting<double>(c, phi_dev, drho_dev, phi0, drho0);
+        if (rc != LBM_OK) return rc;
+    } else if (scheme == LBM_WET_VD) {
+        if (!(scalar > 0) || !(psi_argument(c->p, scalar) >= 0))
+            return fail(LBM_EINVAL, "virtual density outside the range where psi is real");
+    } else if (scheme == LBM_WET_SFI) {
+        if (!std::isfinite(scalar)) return fail(LBM_EINVAL, "G_w must be finite");
+    } else {
+        return fail(LBM_EINVAL, "unknown wetting scheme");
+    }
+    c->scheme = scheme;
+    c->scalar = scalar;
+    return LBM_OK;
+}
+
+int lbm_set_fields(lbm_ctx* c, const void* rho_dev, const void* u_dev) {
+    if (!c || !rho_dev) return fail(LBM_EINVAL, "NULL argument");
+    if (!c->have_geom) return fail(LBM_ESTATE, "set the geometry before the fields");
+    const int64_t QN = (int64_t)c->Q * c->N;
+    if (c->prec == 4) {
+        LBM_HIP(launch_init_eq<float>(c->Q, c->cls, (const float*)rho_dev, (const float*)u_dev,
+                                      (float*)c->f[c->cur], c->N, c->stream));
+        LBM_HIP(launch_fill<float>((float*)c->f[c->cur ^ 1], 0.f, QN, c->stream));
+    } else {
+        LBM_HIP(launch_init_eq<double>(c->Q, c->cls, (const double*)rho_dev,
+                                       (const double*)u_dev, (double*)c->f[c->cur], c->N,
+                                       c->stream));
+        LBM_HIP(launch_fill<double>((double*)c->f[c->cur ^ 1], 0.0, QN, c->stream));
+    }
+    LBM_HIP(launch_fill_i32(c->flag, 0, 4, c->stream));
+    c->have_fields = true;
+    c->domain_error = false;
+    return LBM_OK;
+}
+
+int lbm_set_state(lbm_ctx* c, const void* f_dev) {
+    if (!c || !f_dev) return fail(LBM_EINVAL, "NULL argument");
+    if (!c->have_geom) return fail(LBM_ESTATE, "set the geometry before the state");
+    const int64_t QN = (int64_t)c->Q * c->N;
+    LBM_HIP(hipMemcpyAsync(c->f[c->cur], f_dev, (size_t)QN * c->prec, hipMemcpyDeviceToDevice,
+                           c->stream));
+    if (c->prec == 4) {
+        LBM_HIP(launch_mask_solid<float>(c->Q, c->cls, (float*)c->f[c->cur], c->N, c->stream));
+        LBM_HIP(launch_fill<float>((float*)c->f[c->cur ^ 1], 0.f, QN, c->stream));
+    } else {
+        LBM_HIP(launch_mask_solid<double>(c->Q, c->cls, (double*)c->f[c->cur], c->N, c->stream));
+        LBM_HIP(launch_fill<double>((double*)c->f[c->cur ^ 1], 0.0, QN, c->stream));
+    }
+    LBM_HIP(launch_fill_i32(c->flag, 0, 4, c->stream));
+    c->have_fields = true;
+    c->domain_error = false;
+    return LBM_OK;
+}
+
+int lbm_step(lbm_ctx* c, int64_t nsteps) {
+    if (!c) return fail(LBM_EINVAL, "NULL context");
+    if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
+    if (!c->have_geom || !c->have_fields) return fail(LBM_ESTATE, "geometry and fields must be set");
+    if (c->domain_error) return fail(LBM_EDOMAIN, "a previous step left the psi domain");
+    return c->prec == 4 ? run_steps<float>(c, nsteps) : run_steps<double>(c, nsteps);
+}
+
+int lbm_step_timed(lbm_ctx* c, int64_t nsteps, double* ms_total) {
+    if (!c || !ms_total) return fail(LBM_EINVAL, "NULL argument");
+    if (!c->have_geom || !c->have_fields) return fail(LBM_ESTATE, "geometry and fields must be set");
+    if (c->domain_error) return fail(LBM_EDOMAIN, "a previous step left the psi domain");
+    LBM_HIP(hipEventRecord(c->ev0, c->stream));
+    int rc = c->prec == 4 ? run_steps<float>(c, nsteps) : run_steps<double>(c, nsteps);
+    if (rc != LBM_OK) return rc;
+    LBM_HIP(hipEventRecord(c->ev1, c->stream));
+    LBM_HIP(hipEventSynchronize(c->ev1));
+    float ms = 0.f;
+    LBM_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    *ms_total = ms;
+    return LBM_OK;
+}
+
+int lbm_get_fields(lbm_ctx* c, void* rho_dev, void* u_dev, void* f_dev) {
+    if (!c) return fail(LBM_EINVAL, "NULL context");
+    if (!c->have_geom || !c->have_fields) return fail(LBM_ESTATE, "geometry and fields must be set");
+    if (rho_dev || u_dev) {
+        int rc = c->prec == 4 ? launch_mode<float>(c, MODE_FIELDS, (float*)rho_dev, (float*)u_dev, nullptr)
+                              : launch_mode<double>(c, MODE_FIELDS, (double*)rho_dev,
+                                                    (double*)u_dev, nullptr);
+        if (rc != LBM_OK) return rc;
+    }
+    if (f_dev)
+        LBM_HIP(hipMemcpyAsync(f_dev, c->f[c->cur], (size_t)c->Q * c->N * c->prec,
+                               hipMemcpyDeviceToDevice, c->stream));
+    return LBM_OK;
+}
+
+int lbm_get_diagnostics(lbm_ctx* c, lbm_diag* out) {
+    if (!c || !out) return fail(LBM_EINVAL, "NULL argument");
+    if (!c->have_geom || !c->have_fields) return fail(LBM_ESTATE, "geometry and fields must be set");
+    int rc = c->prec == 4 ? launch_mode<float>(c, MODE_FIELDS, nullptr, nullptr, c->part)
+                          : launch_mode<double>(c, MODE_FIELDS, nullptr, nullptr, c->part);
+    if (rc != LBM_OK) return rc;
+    LBM_HIP(launch_diag_final(c->part, c->nparts, c->diag_out, c->stream));
+    double h[5];
+    int32_t flag[4];
+    LBM_HIP(hipMemcpyAsync(h, c->diag_out, sizeof h, hipMemcpyDeviceToHost, c->stream));
+    LBM_HIP(hipMemcpyAsync(flag, c->flag, sizeof flag, hipMemcpyDeviceToHost, c->stream));
+    LBM_HIP(hipStreamSynchronize(c->stream));
+    out->mass = h[0];
+    out->max_u = h[1];
+    out->rho_min = h[2];
+    out->rho_max = h[3];
+    out->n_fluid = (int32_t)h[4];
+    out->flag = flag[0];
+    if (flag[0]) {
+        c->domain_error = true;
+        return fail(LBM_EDOMAIN, "psi argument became negative or NaN");
+    }
+    return LBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,122 @@
+// aux.hip -- small kernels around the step: equilibrium initialisation,
+// clearing solid slots, fills, and the final pass of the diagnostics.
+#include "lbm_kernels.hpp"
+
+namespace lbm {
+
+template <typename L, typename real>
+__global__ void k_init_eq(const uint8_t* __restrict__ cls, const real* __restrict__ rho,
+                          const real* __restrict__ u, real* __restrict__ f, int64_t N) {
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    const bool fluid = cls[n] == CLS_FLUID;
+    real uu[3] = {real(0), real(0), real(0)};
+    if (fluid && u) {
+#pragma unroll
+        for (int d = 0; d < L::D; ++d) uu[d] = u[d * N + n];
+    }
+    const real r = fluid ? rho[n] : real(0);
+#pragma unroll
+    for (int a = 0; a < L::Q; ++a) f[a * N + n] = fluid ? feq<L, real>(a, r, uu) : real(0);
+}
+
+template <typename real>
+__global__ void k_mask_solid(int Q, const uint8_t* __restrict__ cls, real* __restrict__ f,
+                             int64_t N) {
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N || cls[n] == CLS_FLUID) return;
+    for (int a = 0; a < Q; ++a) f[a * N + n] = real(0);
+}
+
+template <typename T>
+__global__ void k_fill(T* p, T v, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// one workgroup: fixed-order reduction of the per-tile partials
+__global__ void k_diag_final(const double* __restrict__ part, int nparts, double* out) {
+    __shared__ double s_sum[256], s_umax[256], s_rmin[256], s_rmax[256], s_cnt[256];
+    const int t = threadIdx.x;
+    double sum = 0.0, umax = 0.0, rmin = 1e300, rmax = -1e300, cnt = 0.0;
+    for (int i = t; i < nparts; i += 256) {
+        const double* p = part + 5 * i;
+        sum += p[0];
+        umax = p[1] > umax ? p[1] : umax;
+        rmin = p[2] < rmin ? p[2] : rmin;
+        rmax = p[3] > rmax ? p[3] : rmax;
+        cnt += p[4];
+    }
+    s_sum[t] = sum;
+    s_umax[t] = umax;
+    s_rmin[t] = rmin;
+    s_rmax[t] = rmax;
+    s_cnt[t] = cnt;
+    __syncthreads();
+    for (int off = 128; off >= 1; off >>= 1) {
+        if (t < off) {
+            s_sum[t] += s_sum[t + off];
+            s_umax[t] = s_umax[t + off] > s_umax[t] ? s_umax[t + off] : s_umax[t];
+            s_rmin[t] = s_rmin[t + off] < s_rmin[t] ? s_rmin[t + off] : s_rmin[t];
+            s_rmax[t] = s_rmax[t + off] > s_rmax[t] ? s_rmax[t + off] : s_rmax[t];
+            s_cnt[t] += s_cnt[t + off];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        out[0] = s_sum[0];
+        out[1] = s_umax[0];
+        out[2] = s_rmin[0];
+        out[3] = s_rmax[0];
+        out[4] = s_cnt[0];
+    }
+}
+
+static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+template <typename real>
+hipError_t launch_init_eq(int lattice, const uint8_t* cls, const real* rho, const real* u,
+                          real* f, int64_t N, hipStream_t s) {
+    if (lattice == 9)
+        hipLaunchKernelGGL((k_init_eq<D2Q9, real>), dim3(nblk(N, 256)), dim3(256), 0, s, cls, rho,
+                           u, f, N);
+    else
+        hipLaunchKernelGGL((k_init_eq<D3Q19, real>), dim3(nblk(N, 256)), dim3(256), 0, s, cls,
+                           rho, u, f, N);
+    return hipGetLastError();
+}
+
+template <typename real>
+hipError_t launch_mask_solid(int Q, const uint8_t* cls, real* f, int64_t N, hipStream_t s) {
+    hipLaunchKernelGGL((k_mask_solid<real>), dim3(nblk(N, 256)), dim3(256), 0, s, Q, cls, f, N);
+    return hipGetLastError();
+}
+
+template <typename real>
+hipError_t launch_fill(real* p, real v, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_fill<real>), dim3(nblk(n, 256)), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_fill<int32_t>), dim3(nblk(n, 256)), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag_final(const double* part, int nparts, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, s, part, nparts, out);
+    return hipGetLastError();
+}
+
+template hipError_t launch_init_eq<float>(int, const uint8_t*, const float*, const float*, float*,
+                                          int64_t, hipStream_t);
+template hipError_t launch_init_eq<double>(int, const uint8_t*, const double*, const double*,
+                                           double*, int64_t, hipStream_t);
+template hipError_t launch_mask_solid<float>(int, const uint8_t*, float*, int64_t, hipStream_t);
+template hipError_t launch_mask_solid<double>(int, const uint8_t*, double*, int64_t, hipStream_t);
+template hipError_t launch_fill<float>(float*, float, int64_t, hipStream_t);
+template hipError_t launch_fill<double>(double*, double, int64_t, hipStream_t);
+
+}  // namespace lbm

@@ -1,0 +1,92 @@
+// lbm_host.hpp -- host-side internals of the C-ABI library: the context
+// object, status helpers, geometry preprocessing and EOS helpers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "lbm_kernels.hpp"
+
+namespace lbm {
+
+// ---- status
+int fail(int code, const std::string& msg);
+int ok();
+#define LBM_HIP(call)                                                              \
+    do {                                                                           \
+        hipError_t e_ = (call);                                                    \
+        if (e_ != hipSuccess)                                                      \
+            return ::lbm::fail(LBM_EDEVICE, std::string(#call) + ": " +            \
+                                                hipGetErrorString(e_));            \
+    } while (0)
+
+// ---- equation of state (thermo.cpp)
+double eos_pressure(const lbm_params& p, double rho);
+double pr_Tc(double a, double b, double R);
+double pr_aphi(const lbm_params& p);
+double psi_argument(const lbm_params& p, double rho);
+int eos_critical(int eos, double a, double b, double R, double omega, double* Tc, double* rhoc);
+int eos_coexistence(const lbm_params& p, double* rho_g, double* rho_l);
+
+// ---- validation
+int validate(const lbm_params* p);
+
+// ---- geometry (geometry.cpp)
+// node class per node and the increasing list of wall nodes (solid nodes
+// with a fluid neighbour along a non-rest lattice velocity)
+struct Geometry {
+    std::vector<uint8_t> cls;
+    std::vector<int32_t> widx;
+    std::vector<int64_t> walls;
+    int64_t n_fluid = 0;
+};
+int build_geometry(const lbm_params& p, const uint8_t* solid, Geometry& g);
+
+// ---- workspace carving
+struct Carver {
+    char* base;
+    size_t off = 0, cap;
+    Carver(void* b, size_t c) : base((char*)b), cap(c) {}
+    template <typename T>
+    T* take(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+}  // namespace lbm
+
+// the context (opaque in the C ABI)
+struct lbm_ctx {
+    lbm_params p;
+    int Q = 9, D = 2;
+    int64_t N = 0;
+    int prec = 4;
+    hipStream_t stream = nullptr;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    int64_t n_wall_max = 0;
+    // carved device arrays
+    void* f[2] = {nullptr, nullptr};
+    int cur = 0;
+    uint8_t* cls = nullptr;
+    int32_t* widx = nullptr;
+    int32_t* wall_list = nullptr;
+    void* phi = nullptr;
+    void* drho = nullptr;
+    int32_t* flag = nullptr;
+    double* part = nullptr;
+    double* diag_out = nullptr;
+    int nparts = 0;
+    // host state
+    lbm::Geometry geom;
+    bool have_geom = false, have_fields = false, domain_error = false;
+    int scheme = LBM_WET_IVD;
+    double scalar = 0.0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};

@@ -1,0 +1,94 @@
+// lbm_kernels.hpp -- launchers of the HIP kernels and the small device
+// helpers the kernels share (wave64 / LDS reductions).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbm_device.hpp"
+
+namespace lbm {
+
+enum { MODE_STEP = 0, MODE_FIELDS = 1 };
+
+// Outputs of the field mode of a step kernel: macroscopic fields and
+// per-workgroup diagnostic partials (sum rho, max |u|, min rho, max rho,
+// fluid count), each may be null.
+template <typename real>
+struct FieldOut {
+    real* rho;
+    real* u;
+    double* part;
+};
+
+// wave64 butterfly reduction followed by a fixed-order pass over the waves of
+// the workgroup: the result does not depend on scheduling.
+template <int NT, typename real>
+__device__ __forceinline__ void block_reduce_diag(double sum, real umax, real rmin, real rmax,
+                                                  int cnt, double* out) {
+    constexpr int NW = NT / 64;
+    __shared__ double r_sum[NW], r_umax[NW], r_rmin[NW], r_rmax[NW];
+    __shared__ int r_cnt[NW];
+    double du = (double)umax, dmn = (double)rmin, dmx = (double)rmax;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        sum += __shfl_xor(sum, off, 64);
+        double t = __shfl_xor(du, off, 64);
+        du = t > du ? t : du;
+        t = __shfl_xor(dmn, off, 64);
+        dmn = t < dmn ? t : dmn;
+        t = __shfl_xor(dmx, off, 64);
+        dmx = t > dmx ? t : dmx;
+        cnt += __shfl_xor(cnt, off, 64);
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) {
+        r_sum[wv] = sum;
+        r_umax[wv] = du;
+        r_rmin[wv] = dmn;
+        r_rmax[wv] = dmx;
+        r_cnt[wv] = cnt;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = r_sum[0], a = r_umax[0], b = r_rmin[0], c = r_rmax[0];
+        int n = r_cnt[0];
+        for (int i = 1; i < NW; ++i) {
+            s += r_sum[i];
+            a = r_umax[i] > a ? r_umax[i] : a;
+            b = r_rmin[i] < b ? r_rmin[i] : b;
+            c = r_rmax[i] > c ? r_rmax[i] : c;
+            n += r_cnt[i];
+        }
+        out[0] = s;
+        out[1] = a;
+        out[2] = b;
+        out[3] = c;
+        out[4] = (double)n;
+    }
+}
+
+// fused steps
+template <typename real>
+int grid2d_blocks(int nx, int ny);
+template <typename real>
+hipError_t launch_step2d(const Coef<real>& C, const Fields<real>& F, const FieldOut<real>& O,
+                         int mode, hipStream_t s);
+template <typename real>
+int grid3d_blocks(int nx, int ny, int nz);
+template <typename real>
+hipError_t launch_step3d(const Coef<real>& C, const Fields<real>& F, const FieldOut<real>& O,
+                         int mode, hipStream_t s);
+
+// auxiliary kernels
+template <typename real>
+hipError_t launch_init_eq(int lattice, const uint8_t* cls, const real* rho, const real* u,
+                          real* f, int64_t N, hipStream_t s);
+template <typename real>
+hipError_t launch_mask_solid(int Q, const uint8_t* cls, real* f, int64_t N, hipStream_t s);
+template <typename real>
+hipError_t launch_fill(real* p, real v, int64_t n, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+hipError_t launch_diag_final(const double* part, int nparts, double* out, hipStream_t s);
+
+}  // namespace lbm

@@ -1,0 +1,331 @@
+// step_march.hip -- fused time step that sweeps a tile along the last axis
+// (z for D3Q19, y for D2Q9).
+//
+// Same arithmetic as the tiled 2-D step (Sec. II A, Sec. III B: density,
+// psi, wall virtual density, force, velocity, MRT collision with the Eq. 7
+// forcing, push streaming with halfway bounce-back).  A workgroup owns a
+// TX x TY column of the cross-section (TY = 1 in 2-D) and a chunk of TZ
+// slices along the sweep axis.  It walks the chunk plus two halo slices on
+// each side; for each slice it
+//   A  loads node classes and densities of the cross-section tile plus a
+//      2-node halo into slot (it mod 5) of an LDS ring; owned nodes keep
+//      their populations in a 3-deep register pipeline,
+//   B  finishes the wall virtual densities and psi of the previous slice on
+//      the tile plus a 1-node halo (ring of 4 psi slots),
+//   C  collides and streams the slice two behind the load front.
+// Only the cross-section halo is re-read (from L2); along the sweep axis
+// each slice is read once per chunk, so the re-read fraction is
+// (TZ+4)/TZ * (ring / tile) instead of the cube of a 3-D halo.
+#include "lbm_device.hpp"
+#include "lbm_kernels.hpp"
+
+namespace lbm {
+
+template <typename L, typename real, int TX, int TY, int TZ, int MODE>
+__global__ __launch_bounds__(TX* TY) void k_step_march(Coef<real> C, Fields<real> Fd,
+                                                       FieldOut<real> Out) {
+    constexpr bool D3 = (L::D == 3);
+    constexpr int Q = L::Q;
+    constexpr int NT = TX * TY;
+    constexpr int HB = D3 ? 2 : 0;           // halo along the second tile axis
+    constexpr int PA = TX + 4, PB = TY + 2 * HB, PS = PA * PB;
+    constexpr int RING = PS - TX * TY;
+    static_assert(RING <= NT, "each thread handles at most one halo position");
+    constexpr int NSLOT = 5, NPSI = 4;
+
+    __shared__ uint8_t s_cls[NSLOT][PS];
+    __shared__ real s_rho[NSLOT][PS];
+    __shared__ real s_psi[NPSI][PS];
+
+    const int na = C.nx;
+    const int nb = D3 ? C.ny : 1;
+    const int nc = D3 ? C.nz : C.ny;
+    const size_t nab = (size_t)na * nb;
+    const size_t N = nab * nc;
+    const int tid = threadIdx.x;
+    const int a0 = blockIdx.x * TX, b0 = blockIdx.y * TY, c0 = blockIdx.z * TZ;
+
+    // owned position of this thread and its halo position (if any)
+    const int own_la = 2 + tid % TX, own_lb = HB + tid / TX;
+    int ring_la = -1, ring_lb = -1;
+    if (tid < RING) {
+        // enumerate the plane positions outside the owned TX x TY block
+        int cnt = 0;
+        if (D3) {
+            // two full rows below and above, then two columns on each side
+            if (tid < 2 * PA) {
+                ring_lb = tid / PA;
+                ring_la = tid % PA;
+            } else if (tid < 4 * PA) {
+                ring_lb = TY + 2 + (tid - 2 * PA) / PA;
+                ring_la = (tid - 2 * PA) % PA;
+            } else {
+                const int j = tid - 4 * PA;
+                ring_lb = 2 + j / 4;
+                const int c = j % 4;
+                ring_la = c < 2 ? c : TX + c;
+            }
+        } else {
+            ring_lb = 0;
+            ring_la = tid < 2 ? tid : TX + tid;
+        }
+        (void)cnt;
+    }
+    const int own_a = a0 + own_la - 2, own_b = b0 + own_lb - HB;
+    const bool own_in = own_a < na && own_b < nb;  // ragged tiles
+    const size_t own_ab = (size_t)wrapi(own_b, nb) * na + wrapi(own_a, na);
+    size_t ring_ab = 0;
+    if (tid < RING) ring_ab = (size_t)wrapi(b0 + ring_lb - HB, nb) * na + wrapi(a0 + ring_la - 2, na);
+    const int own_p = own_lb * PA + own_la;
+    const int ring_p = (tid < RING) ? ring_lb * PA + ring_la : 0;
+
+    real f0[Q], f1[Q], f2[Q];  // populations of the slices it, it-1, it-2
+#pragma unroll
+    for (int a = 0; a < Q; ++a) f0[a] = f1[a] = f2[a] = real(0);
+    bool bad = false;
+    double d_sum = 0.0;
+    real d_umax = real(0), d_rmin = real(1e30), d_rmax = real(-1e30);
+    int d_cnt = 0;
+
+    for (int it = 0; it < TZ + 4; ++it) {
+        // ---------------- A: slice c0 - 2 + it
+        {
+            const int slot = it % NSLOT;
+            const int cz = wrapi(c0 - 2 + it, nc);
+            const size_t base = (size_t)cz * nab;
+            // shift the register pipeline
+#pragma unroll
+            for (int a = 0; a < Q; ++a) {
+                f2[a] = f1[a];
+                f1[a] = f0[a];
+            }
+            const uint8_t co = Fd.cls[base + own_ab];
+            s_cls[slot][own_p] = co;
+            real r = real(0);
+            if (co == CLS_FLUID) {
+#pragma unroll
+                for (int a = 0; a < Q; ++a) f0[a] = Fd.fin[a * N + base + own_ab];
+                r = f0[0];
+#pragma unroll
+                for (int a = 1; a < Q; ++a) r += f0[a];
+            } else {
+#pragma unroll
+                for (int a = 0; a < Q; ++a) f0[a] = real(0);
+            }
+            s_rho[slot][own_p] = r;
+            if (tid < RING) {
+                const uint8_t cr = Fd.cls[base + ring_ab];
+                s_cls[slot][ring_p] = cr;
+                real rr = real(0);
+                if (cr == CLS_FLUID) {
+                    rr = Fd.fin[base + ring_ab];
+#pragma unroll
+                    for (int a = 1; a < Q; ++a) rr += Fd.fin[a * N + base + ring_ab];
+                }
+                s_rho[slot][ring_p] = rr;
+            }
+        }
+        __syncthreads();
+        // ---------------- B: psi (and wall densities) of slice c0 - 3 + it
+        if (it >= 2) {
+            const int sc = (it - 1) % NSLOT;
+            const int sp = (it - 1) % NPSI;
+            const int cz = wrapi(c0 - 3 + it, nc);
+            constexpr int TA = TX + 2, TB = D3 ? TY + 2 : 1;
+            for (int i = tid; i < TA * TB; i += NT) {
+                const int la = 1 + i % TA;
+                const int lb = D3 ? 1 + i / TA : 0;
+                const int p = lb * PA + la;
+                const uint8_t c = s_cls[sc][p];
+                real ps = real(0);
+                if (c == CLS_FLUID) {
+                    ps = psi_of(C, s_rho[sc][p], bad);
+                } else if (c == CLS_WALL) {
+                    if (C.scheme == WET_IVD) {
+                        real num = real(0), den = real(0);
+                        bool first = true;
+#pragma unroll
+                        for (int a = 1; a < Q; ++a) {
+                            const int ea = L::ex[a];
+                            const int eb = D3 ? L::ey[a] : 0;
+                            const int ec = D3 ? L::ez[a] : L::ey[a];
+                            const int s2 = (it - 1 + ec + NSLOT) % NSLOT;
+                            const int q = p + ea + eb * PA;
+                            if (s_cls[s2][q] == CLS_FLUID) {
+                                const real w = real(L::w12[a]) * real(1.0 / 12.0);
+                                num = first ? w * s_rho[s2][q] : num + w * s_rho[s2][q];
+                                den = first ? w : den + w;
+                                first = false;
+                            }
+                        }
+                        const real rave = num / den;
+                        const size_t n = (size_t)cz * nab +
+                                         (size_t)wrapi(b0 + lb - HB, nb) * na + wrapi(a0 + la - 2, na);
+                        const int kw = Fd.widx[n];
+                        real rw = Fd.phi[kw] * rave - Fd.drho[kw];
+                        rw = rw > C.rho_l ? C.rho_l : rw;
+                        rw = rw < C.rho_g ? C.rho_g : rw;
+                        s_rho[sc][p] = rw;
+                        ps = psi_of(C, rw, bad);
+                    } else if (C.scheme == WET_VD) {
+                        s_rho[sc][p] = C.rho_w;
+                        ps = C.psi_w;
+                    } else {
+                        s_rho[sc][p] = real(0);
+                    }
+                }
+                s_psi[sp][p] = ps;
+            }
+        }
+        __syncthreads();
+        // ---------------- C: collide and stream slice c0 - 4 + it
+        const int cc = c0 - 4 + it;
+        if (it >= 4 && cc < nc && own_in) {
+            const int sc = (it - 2) % NSLOT;
+            const int sp = (it - 2) % NPSI;
+            const size_t n = (size_t)cc * nab + own_ab;
+            const uint8_t c = s_cls[sc][own_p];
+            if (c != CLS_FLUID) {
+                if (MODE == MODE_FIELDS) {
+                    if (Out.rho) Out.rho[n] = (c == CLS_WALL) ? s_rho[sc][own_p] : real(0);
+                    if (Out.u)
+                        for (int d = 0; d < L::D; ++d) Out.u[d * N + n] = real(0);
+                }
+            } else {
+                const real rho = s_rho[sc][own_p];
+                const real psi_c = s_psi[sp][own_p];
+                real sm[3] = {real(0), real(0), real(0)}, sa[3] = {real(0), real(0), real(0)};
+#pragma unroll
+                for (int a = 1; a < Q; ++a) {
+                    const int ea = L::ex[a];
+                    const int eb = D3 ? L::ey[a] : 0;
+                    const int ec = D3 ? L::ez[a] : L::ey[a];
+                    const int q = own_p + ea + eb * PA;
+                    const int s2 = (it - 2 + ec + NPSI) % NPSI;
+                    const real w = real(L::w12[a]) * real(1.0 / 12.0);
+                    const real wp = w * s_psi[s2][q];
+                    const int e3[3] = {L::ex[a], L::ey[a], L::ez[a]};
+#pragma unroll
+                    for (int d = 0; d < L::D; ++d) {
+                        if (e3[d] == 1) sm[d] += wp;
+                        if (e3[d] == -1) sm[d] -= wp;
+                    }
+                    if (C.scheme == WET_SFI) {
+                        const int s3 = (it - 2 + ec + NSLOT) % NSLOT;
+                        if (s_cls[s3][q] != CLS_FLUID) {
+#pragma unroll
+                            for (int d = 0; d < L::D; ++d) {
+                                if (e3[d] == 1) sa[d] += w;
+                                if (e3[d] == -1) sa[d] -= w;
+                            }
+                        }
+                    }
+                }
+                real Fm[3], F[3];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    Fm[d] = (d < L::D) ? -C.G * psi_c * sm[d] : real(0);
+                    const real fa = (C.scheme == WET_SFI) ? -C.G_w * rho * sa[d] : real(0);
+                    F[d] = (d < L::D) ? Fm[d] + fa + C.body[d] : real(0);
+                }
+                if (MODE == MODE_FIELDS) {
+                    real j[3] = {real(0), real(0), real(0)};
+#pragma unroll
+                    for (int a = 0; a < Q; ++a) {
+                        const int e3[3] = {L::ex[a], L::ey[a], L::ez[a]};
+#pragma unroll
+                        for (int d = 0; d < L::D; ++d) {
+                            if (e3[d] == 1) j[d] += f2[a];
+                            if (e3[d] == -1) j[d] -= f2[a];
+                        }
+                    }
+                    real uu = real(0);
+#pragma unroll
+                    for (int d = 0; d < L::D; ++d) {
+                        const real ud = (j[d] + real(0.5) * F[d]) / rho;
+                        if (Out.u) Out.u[d * N + n] = ud;
+                        uu += ud * ud;
+                    }
+                    if (Out.rho) Out.rho[n] = rho;
+                    const real um = sqrt(uu);
+                    d_sum += (double)rho;
+                    d_umax = um > d_umax ? um : d_umax;
+                    d_rmin = rho < d_rmin ? rho : d_rmin;
+                    d_rmax = rho > d_rmax ? rho : d_rmax;
+                    d_cnt += 1;
+                } else {
+                    real fs[Q], u[3];
+                    collide<L, real>(C, f2, rho, F, Fm, psi_c, fs, u);
+                    const int ga = own_a, gb = D3 ? own_b : 0;
+#pragma unroll
+                    for (int a = 0; a < Q; ++a) {
+                        const int ea = L::ex[a];
+                        const int eb = D3 ? L::ey[a] : 0;
+                        const int ec = D3 ? L::ez[a] : L::ey[a];
+                        const int s3 = (it - 2 + ec + NSLOT) % NSLOT;
+                        const int q = own_p + ea + eb * PA;
+                        if (s_cls[s3][q] == CLS_FLUID) {
+                            int ta = ga + ea, tb = gb + eb, tc = cc + ec;
+                            ta = ta < 0 ? ta + na : (ta >= na ? ta - na : ta);
+                            tb = tb < 0 ? tb + nb : (tb >= nb ? tb - nb : tb);
+                            tc = tc < 0 ? tc + nc : (tc >= nc ? tc - nc : tc);
+                            Fd.fout[a * N + (size_t)tc * nab + (size_t)tb * na + ta] = fs[a];
+                        } else {
+                            Fd.fout[L::opp[a] * N + n] = fs[a];
+                        }
+                    }
+                }
+            }
+        }
+        // no barrier here: the next phase A writes slot (it+1) mod 5, which
+        // phase C of this iteration does not read (it reads it-3 .. it-1)
+    }
+
+    if (MODE == MODE_FIELDS && Out.part) {
+        block_reduce_diag<NT>(d_sum, d_umax, d_rmin, d_rmax, d_cnt,
+                              Out.part + 5 * ((blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x +
+                                              blockIdx.x));
+    }
+    if (bad) Fd.flag[0] = 1;
+}
+
+// ----------------------------------------------------------------- launch
+template <typename real>
+struct Tile3D;
+template <>
+struct Tile3D<float> {
+    static constexpr int TX = 32, TY = 8, TZ = 16;
+};
+template <>
+struct Tile3D<double> {
+    static constexpr int TX = 32, TY = 8, TZ = 16;
+};
+
+template <typename real>
+int grid3d_blocks(int nx, int ny, int nz) {
+    using T = Tile3D<real>;
+    return ((nx + T::TX - 1) / T::TX) * ((ny + T::TY - 1) / T::TY) * ((nz + T::TZ - 1) / T::TZ);
+}
+
+template <typename real>
+hipError_t launch_step3d(const Coef<real>& C, const Fields<real>& F, const FieldOut<real>& O,
+                         int mode, hipStream_t s) {
+    using T = Tile3D<real>;
+    dim3 grid((C.nx + T::TX - 1) / T::TX, (C.ny + T::TY - 1) / T::TY, (C.nz + T::TZ - 1) / T::TZ);
+    if (mode == MODE_STEP)
+        hipLaunchKernelGGL((k_step_march<D3Q19, real, T::TX, T::TY, T::TZ, MODE_STEP>), grid,
+                           dim3(T::TX * T::TY), 0, s, C, F, O);
+    else
+        hipLaunchKernelGGL((k_step_march<D3Q19, real, T::TX, T::TY, T::TZ, MODE_FIELDS>), grid,
+                           dim3(T::TX * T::TY), 0, s, C, F, O);
+    return hipGetLastError();
+}
+
+template int grid3d_blocks<float>(int, int, int);
+template int grid3d_blocks<double>(int, int, int);
+template hipError_t launch_step3d<float>(const Coef<float>&, const Fields<float>&,
+                                         const FieldOut<float>&, int, hipStream_t);
+template hipError_t launch_step3d<double>(const Coef<double>&, const Fields<double>&,
+                                          const FieldOut<double>&, int, hipStream_t);
+
+}  // namespace lbm

@@ -1,0 +1,293 @@
+"""Thin ctypes binding of the C ABI in include/lbm.h.
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of liblbm.so.  PyTorch provides device memory (the workspace and the field
+tensors) and the stream.  There is no CPU fallback: if the library is not
+built, loading fails with an error.
+
+The functions carry the C names (lbm_create, lbm_set_geometry, ...); the
+`Solver` class is a convenience wrapper that owns a workspace tensor.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+import torch  # must be imported before liblbm.so so both share one HIP runtime
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbm.so")
+
+LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDOMAIN, LBM_ESTATE, LBM_EDEVICE = 0, -1, -2, -3, -4, -5
+LBM_EOS_CS, LBM_EOS_PR = 0, 1
+LBM_WET_IVD, LBM_WET_VD, LBM_WET_SFI = 0, 1, 2
+
+
+class lbm_params(C.Structure):
+    _fields_ = [
+        ("lattice", C.c_int32), ("precision", C.c_int32), ("nx", C.c_int32),
+        ("ny", C.c_int32), ("nz", C.c_int32), ("eos", C.c_int32),
+        ("tau", C.c_double * 19), ("eos_a", C.c_double), ("eos_b", C.c_double),
+        ("eos_R", C.c_double), ("eos_T", C.c_double), ("eos_omega", C.c_double),
+        ("G", C.c_double), ("sigma", C.c_double), ("body_force", C.c_double * 3),
+        ("rho_g", C.c_double), ("rho_l", C.c_double),
+    ]
+
+
+class lbm_diag(C.Structure):
+    _fields_ = [("mass", C.c_double), ("max_u", C.c_double), ("rho_min", C.c_double),
+                ("rho_max", C.c_double), ("flag", C.c_int32), ("n_fluid", C.c_int32)]
+
+
+class LBMError(RuntimeError):
+    def __init__(self, code, where, msg):
+        super().__init__(f"{where}: {msg} (code {code})")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load liblbm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_1908_04443_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, P, i64, dp = C.c_void_p, C.POINTER(lbm_params), C.c_int64, C.POINTER(C.c_double)
+        sig = {
+            "lbm_version": (C.c_char_p, []),
+            "lbm_status_string": (C.c_char_p, [C.c_int]),
+            "lbm_last_error": (C.c_char_p, []),
+            "lbm_validate_params": (C.c_int, [P]),
+            "lbm_eos_critical": (C.c_int, [C.c_int32, C.c_double, C.c_double, C.c_double,
+                                           C.c_double, dp, dp]),
+            "lbm_eos_coexistence": (C.c_int, [P, dp, dp]),
+            "lbm_eos_eval": (C.c_int, [P, C.c_double, dp, dp]),
+            "lbm_workspace_bytes": (C.c_size_t, [P, i64]),
+            "lbm_create": (C.c_int, [P, vp, vp, C.c_size_t, i64, C.POINTER(vp)]),
+            "lbm_destroy": (C.c_int, [vp]),
+            "lbm_set_geometry": (C.c_int, [vp, C.POINTER(C.c_uint8)]),
+            "lbm_wall_nodes": (C.c_int, [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+            "lbm_set_wetting": (C.c_int, [vp, C.c_int32, C.c_double, vp, vp, C.c_double,
+                                          C.c_double]),
+            "lbm_set_fields": (C.c_int, [vp, vp, vp]),
+            "lbm_set_state": (C.c_int, [vp, vp]),
+            "lbm_step": (C.c_int, [vp, i64]),
+            "lbm_step_timed": (C.c_int, [vp, i64, dp]),
+            "lbm_get_fields": (C.c_int, [vp, vp, vp, vp]),
+            "lbm_get_diagnostics": (C.c_int, [vp, C.POINTER(lbm_diag)]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype, fn.argtypes = res, args
+        _lib = L
+    return _lib
+
+
+def _check(rc, where):
+    if rc != LBM_OK:
+        msg = lib().lbm_last_error().decode()
+        raise LBMError(rc, where, msg)
+    return rc
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+# ------------------------------------------------------------- C-named calls
+def lbm_version():
+    return lib().lbm_version().decode()
+
+
+def lbm_validate_params(p):
+    return lib().lbm_validate_params(C.byref(p))
+
+
+def lbm_eos_critical(eos, a, b, R, omega=0.344):
+    Tc, rc = C.c_double(), C.c_double()
+    _check(lib().lbm_eos_critical(eos, a, b, R, omega, C.byref(Tc), C.byref(rc)),
+           "lbm_eos_critical")
+    return Tc.value, rc.value
+
+
+def lbm_eos_coexistence(p):
+    g, l = C.c_double(), C.c_double()
+    _check(lib().lbm_eos_coexistence(C.byref(p), C.byref(g), C.byref(l)), "lbm_eos_coexistence")
+    return g.value, l.value
+
+
+def lbm_eos_eval(p, rho):
+    pe, ps = C.c_double(), C.c_double()
+    rc = lib().lbm_eos_eval(C.byref(p), float(rho), C.byref(pe), C.byref(ps))
+    return rc, pe.value, ps.value
+
+
+def lbm_workspace_bytes(p, n_wall_max):
+    return lib().lbm_workspace_bytes(C.byref(p), int(n_wall_max))
+
+
+def lbm_create(p, stream, workspace, n_wall_max):
+    ctx = C.c_void_p()
+    _check(lib().lbm_create(C.byref(p), C.c_void_p(stream), _ptr(workspace),
+                            workspace.numel() * workspace.element_size(), int(n_wall_max),
+                            C.byref(ctx)), "lbm_create")
+    return ctx
+
+
+def lbm_destroy(ctx):
+    return lib().lbm_destroy(ctx)
+
+
+def lbm_set_geometry(ctx, solid):
+    s = np.ascontiguousarray(np.asarray(solid, dtype=np.uint8).ravel())
+    _check(lib().lbm_set_geometry(ctx, s.ctypes.data_as(C.POINTER(C.c_uint8))),
+           "lbm_set_geometry")
+
+
+def lbm_wall_nodes(ctx):
+    n = C.c_int64()
+    _check(lib().lbm_wall_nodes(ctx, None, C.byref(n)), "lbm_wall_nodes")
+    idx = np.zeros(max(n.value, 1), dtype=np.int64)
+    _check(lib().lbm_wall_nodes(ctx, idx.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(n)),
+           "lbm_wall_nodes")
+    return idx[:n.value]
+
+
+def lbm_set_wetting(ctx, scheme, scalar=0.0, phi=None, drho=None, phi0=1.0, drho0=0.0):
+    _check(lib().lbm_set_wetting(ctx, int(scheme), float(scalar), _ptr(phi), _ptr(drho),
+                                 float(phi0), float(drho0)), "lbm_set_wetting")
+
+
+def lbm_set_fields(ctx, rho, u=None):
+    _check(lib().lbm_set_fields(ctx, _ptr(rho), _ptr(u)), "lbm_set_fields")
+
+
+def lbm_set_state(ctx, f):
+    _check(lib().lbm_set_state(ctx, _ptr(f)), "lbm_set_state")
+
+
+def lbm_step(ctx, nsteps):
+    _check(lib().lbm_step(ctx, int(nsteps)), "lbm_step")
+
+
+def lbm_step_timed(ctx, nsteps):
+    ms = C.c_double()
+    _check(lib().lbm_step_timed(ctx, int(nsteps), C.byref(ms)), "lbm_step_timed")
+    return ms.value
+
+
+def lbm_get_fields(ctx, rho=None, u=None, f=None):
+    _check(lib().lbm_get_fields(ctx, _ptr(rho), _ptr(u), _ptr(f)), "lbm_get_fields")
+
+
+def lbm_get_diagnostics(ctx):
+    d = lbm_diag()
+    rc = lib().lbm_get_diagnostics(ctx, C.byref(d))
+    if rc not in (LBM_OK, LBM_EDOMAIN):
+        _check(rc, "lbm_get_diagnostics")
+    return rc, dict(mass=d.mass, max_u=d.max_u, rho_min=d.rho_min, rho_max=d.rho_max,
+                    flag=d.flag, n_fluid=d.n_fluid)
+
+
+# ---------------------------------------------------------------- helpers
+def make_params(lattice=9, precision=4, nx=64, ny=64, nz=1, tau=1.0, eos=LBM_EOS_CS,
+                a=1.0, b=4.0, R=1.0, T=None, T_ratio=0.75, omega=0.344, G=-1.0, sigma=0.0,
+                body_force=(0.0, 0.0, 0.0), rho_g=None, rho_l=None):
+    """Parameter block; T defaults to T_ratio * Tc and the limiter bounds to
+    the Maxwell coexistence densities, both from the library's EOS helpers."""
+    p = lbm_params()
+    p.lattice, p.precision, p.nx, p.ny, p.nz, p.eos = lattice, precision, nx, ny, nz, eos
+    taus = np.full(19, float(tau)) if np.ndim(tau) == 0 else np.asarray(tau, float)
+    for i in range(19):
+        p.tau[i] = float(taus[i]) if i < len(taus) else 1.0
+    p.eos_a, p.eos_b, p.eos_R, p.eos_omega = a, b, R, omega
+    if T is None:
+        Tc, _ = lbm_eos_critical(eos, a, b, R, omega)
+        T = T_ratio * Tc
+    p.eos_T = T
+    p.G, p.sigma = G, sigma
+    for i in range(3):
+        p.body_force[i] = body_force[i]
+    if rho_g is None or rho_l is None:
+        p.rho_g, p.rho_l = 0.1, 1.0  # placeholders for the coexistence call
+        g, l = lbm_eos_coexistence(p)
+        rho_g = g if rho_g is None else rho_g
+        rho_l = l if rho_l is None else rho_l
+    p.rho_g, p.rho_l = rho_g, rho_l
+    return p
+
+
+class Solver:
+    """One lattice on one GPU: owns the workspace tensor and the context."""
+
+    def __init__(self, params, n_wall_max, device="cuda:0", stream=None):
+        self.p = params
+        self.device = torch.device(device)
+        self.dtype = torch.float32 if params.precision == 4 else torch.float64
+        self.N = params.nx * params.ny * params.nz
+        self.Q = params.lattice
+        self.D = 2 if params.lattice == 9 else 3
+        nbytes = lbm_workspace_bytes(params, n_wall_max)
+        if nbytes == 0:
+            raise LBMError(LBM_EINVAL, "lbm_workspace_bytes", lib().lbm_last_error().decode())
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ctx = lbm_create(params, self.stream.cuda_stream, self.ws, n_wall_max)
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            lbm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_geometry(self, solid):
+        lbm_set_geometry(self.ctx, solid)
+
+    def wall_nodes(self):
+        return lbm_wall_nodes(self.ctx)
+
+    def set_wetting(self, scheme, scalar=0.0, phi=None, drho=None, phi0=1.0, drho0=0.0):
+        lbm_set_wetting(self.ctx, scheme, scalar, phi, drho, phi0, drho0)
+
+    def set_fields(self, rho, u=None):
+        rho = torch.as_tensor(rho, dtype=self.dtype, device=self.device).contiguous().view(-1)
+        if u is not None:
+            u = torch.as_tensor(u, dtype=self.dtype, device=self.device).contiguous().view(-1)
+        lbm_set_fields(self.ctx, rho, u)
+        self._keep = (rho, u)  # inputs stay alive until the stream consumed them
+
+    def set_state(self, f):
+        f = torch.as_tensor(f, dtype=self.dtype, device=self.device).contiguous()
+        lbm_set_state(self.ctx, f)
+        self._keep = (f,)
+
+    def step(self, n):
+        lbm_step(self.ctx, n)
+
+    def step_timed(self, n):
+        return lbm_step_timed(self.ctx, n)
+
+    def get_fields(self, rho=True, u=True, f=False):
+        r = torch.empty(self.N, dtype=self.dtype, device=self.device) if rho else None
+        v = torch.empty(self.D * self.N, dtype=self.dtype, device=self.device) if u else None
+        g = torch.empty(self.Q * self.N, dtype=self.dtype, device=self.device) if f else None
+        lbm_get_fields(self.ctx, r, v, g)
+        out = {}
+        if rho:
+            out["rho"] = r
+        if u:
+            out["u"] = v.view(self.D, self.N)
+        if f:
+            out["f"] = g.view(self.Q, self.N)
+        return out
+
+    def diagnostics(self):
+        return lbm_get_diagnostics(self.ctx)

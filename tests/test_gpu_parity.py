@@ -1,0 +1,120 @@
+"""GPU library vs CPU oracle, element by element on the same seeded inputs.
+
+Bars: FP64 max-abs on rho <= 1e-12 (after 1000 steps for the 128 x 128
+cylinder-droplet case); FP32 normwise relative on rho <= 1e-4; integer
+results (wall lists) bit-exact.
+"""
+import numpy as np
+import pytest
+
+from cases import Setup, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+C0 = dict(nx=128, ny=128, geometry=("disk", (64, 64), 24), init=("droplet", (64, 108), 20),
+          scheme="ivd", phi=1.2, noise=1e-6, seed=0, precision=8)
+
+
+def _fluid(setup):
+    return setup.solid.ravel() == 0
+
+
+def _compare(O, setup, res, nsteps, tol_rho, tol_u, rel=False):
+    f = O.run(setup.op, setup.solid, setup.f0, nsteps, setup.phi, setup.drho)
+    rho_o, u_o, _ = O.fields(setup.op, setup.solid, f, setup.phi, setup.drho)
+    if rel:
+        err = np.abs(res["rho"] - rho_o).max() / np.abs(rho_o).max()
+        uerr = np.abs(res["u"] - u_o).max() / max(np.abs(u_o).max(), 1e-30)
+    else:
+        err = np.abs(res["rho"] - rho_o).max()
+        uerr = np.abs(res["u"] - u_o).max()
+    print(f"rho err {err:.3e}  u err {uerr:.3e}", flush=True)
+    assert err <= tol_rho
+    assert uerr <= tol_u
+    return f
+
+
+def test_wall_list_matches_oracle(oracle_mod, gpu_lib):
+    s = Setup(oracle_mod, C0)
+    res = run_gpu(gpu_lib, s, 0)
+    assert np.array_equal(res["walls"], s.walls)
+    assert len(s.walls) == 188
+
+
+def test_c0_fp64_1000_steps(oracle_mod, gpu_lib):
+    s = Setup(oracle_mod, C0)
+    res = run_gpu(gpu_lib, s, 1000)
+    _compare(oracle_mod, s, res, 1000, 1e-12, 1e-12)
+
+
+def test_c0_fp32_1000_steps(oracle_mod, gpu_lib):
+    s = Setup(oracle_mod, dict(C0, precision=4))
+    res = run_gpu(gpu_lib, s, 1000)
+    _compare(oracle_mod, s, res, 1000, 1e-4, 1e-3, rel=True)
+
+
+@pytest.mark.parametrize("scheme", ["ivd", "vd", "sfi"])
+def test_ragged_schemes_fp64(oracle_mod, gpu_lib, scheme):
+    # sizes that leave partial tiles in both directions
+    case = dict(nx=50, ny=37, geometry=("disk", (25, 14), 8), init=("droplet", (25, 28), 7),
+                scheme=scheme, rho_w=0.2, G_w=0.05, noise=1e-6, seed=3, precision=8)
+    if scheme == "ivd":
+        rng = np.random.default_rng(5)
+        case["phi_field"] = lambda solid: 1.0 + 0.3 * rng.random(solid.shape)
+        case["drho_field"] = lambda solid: 0.05 * rng.random(solid.shape)
+    s = Setup(oracle_mod, case)
+    res = run_gpu(gpu_lib, s, 300)
+    assert np.array_equal(res["walls"], s.walls)
+    _compare(oracle_mod, s, res, 300, 1e-12, 1e-12)
+
+
+def test_tiny_lattice_wraps(oracle_mod, gpu_lib):
+    # smaller than one tile and than the halo: every LDS position wraps
+    case = dict(nx=6, ny=5, geometry=("mask", np.eye(5, 6, dtype=np.uint8)),
+                init=("uniform", 0.2), noise=1e-3, seed=1, scheme="ivd", phi=1.1, precision=8)
+    s = Setup(oracle_mod, case)
+    res = run_gpu(gpu_lib, s, 40)
+    _compare(oracle_mod, s, res, 40, 1e-12, 1e-12)
+
+
+def test_d3q19_fp64(oracle_mod, gpu_lib):
+    case = dict(lattice=19, nx=20, ny=18, nz=22, T_ratio=0.8, sigma=0.0,
+                geometry=("disk", (10, 9, 9), 5), init=("droplet", (10, 9, 17), 5),
+                scheme="ivd", phi=1.1, noise=1e-6, seed=2, precision=8)
+    s = Setup(oracle_mod, case)
+    res = run_gpu(gpu_lib, s, 60)
+    assert np.array_equal(res["walls"], s.walls)
+    _compare(oracle_mod, s, res, 60, 1e-12, 1e-12)
+
+
+def test_d3q19_fp32(oracle_mod, gpu_lib):
+    case = dict(lattice=19, nx=34, ny=17, nz=19, T_ratio=0.8, sigma=0.0,
+                geometry=("disk", (17, 8, 8), 5), init=("droplet", (17, 8, 15), 4),
+                scheme="ivd", phi=1.0, noise=1e-6, seed=2, precision=4)
+    s = Setup(oracle_mod, case)
+    res = run_gpu(gpu_lib, s, 60)
+    _compare(oracle_mod, s, res, 60, 1e-4, 1e-3, rel=True)
+
+
+def test_body_force_channel_fp64(oracle_mod, gpu_lib):
+    case = dict(nx=8, ny=30, geometry=("channel",), init=("uniform", 0.33), scheme="ivd",
+                phi=1.0, body=(1e-5, 0.0, 0.0), precision=8)
+    s = Setup(oracle_mod, case)
+    res = run_gpu(gpu_lib, s, 500)
+    _compare(oracle_mod, s, res, 500, 1e-12, 1e-12)
+
+
+def test_diagnostics_match_oracle(oracle_mod, gpu_lib):
+    s = Setup(oracle_mod, C0)
+    res = run_gpu(gpu_lib, s, 100)
+    rc, d = res["solver"].diagnostics()
+    assert rc == 0 and d["flag"] == 0
+    f = oracle_mod.run(s.op, s.solid, s.f0, 100, s.phi, s.drho)
+    rho_o, u_o, _ = oracle_mod.fields(s.op, s.solid, f, s.phi, s.drho)
+    fl = _fluid(s)
+    assert d["n_fluid"] == int(fl.sum())
+    assert abs(d["mass"] - rho_o[fl].sum()) <= 1e-11 * rho_o[fl].sum()
+    assert abs(d["rho_min"] - rho_o[fl].min()) <= 1e-12
+    assert abs(d["rho_max"] - rho_o[fl].max()) <= 1e-12
+    umag = np.sqrt((u_o ** 2).sum(0))
+    assert abs(d["max_u"] - umag[fl].max()) <= 1e-12
