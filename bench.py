@@ -1,0 +1,224 @@
+#!/usr/bin/env python3
+"""Throughput of the fused pseudopotential LB step on one MI355X.
+
+Headline workload: D2Q9 MRT, 2048 x 2048, FP32, periodic porous medium of
+400 cylinders (radii U[8, 32], dart throwing), a prescribed contact angle
+per cylinder U[30, 150] deg through the improved virtual-density scheme,
+50/50 liquid/gas blobs, Carnahan-Starling at 0.75 Tc.  A step is one launch
+of the fused kernel over the whole lattice (density, psi, wall virtual
+density, force, MRT collision, streaming with halfway bounce-back).
+
+Prints one JSON line: MLUPS over all nodes (whole job), the HBM roofline of
+the step kernel (algorithmic bytes 2*Q*sizeof(real) per fluid node per
+step, divided by the HIP-event kernel time), the CPU oracle on a bounded
+sample of the same workload, and secondary lines (D3Q19 256^3).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "MLUPS and % HBM roofline (FP32 D2Q9/D3Q19); batched vs single; adjoint/forward time"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("lbm_device.hpp", "step2d.hip", "step_march.hip"):
+        with open(os.path.join(ROOT, "paper_1908_04443_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """Per-launch HBM bytes from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.txt")
+    if not os.path.exists(path):
+        return None
+    want = kernel_source_hash()
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        kv = dict(tok.split("=", 1) for tok in line.split() if "=" in tok)
+        if kv.get("kernel") == kernel and kv.get("workload") == workload and kv.get("src") == want:
+            return float(kv["bytes_per_launch"])
+    return None
+
+
+def setup_solver(L, W, params, data, n_wall_max):
+    import torch
+    s = L.Solver(params, n_wall_max)
+    s.set_geometry(data["solid"])
+    walls = s.wall_nodes()
+    phi = torch.as_tensor(data["phi"].ravel()[walls], dtype=s.dtype, device=s.device)
+    drho = torch.as_tensor(data["drho"].ravel()[walls], dtype=s.dtype, device=s.device)
+    s.set_wetting(L.LBM_WET_IVD, 0.0, phi if len(walls) else None, drho if len(walls) else None)
+    s.set_fields(data["rho"].ravel())
+    return s, len(walls)
+
+
+def time_steps(s, warmup, steps):
+    import torch
+    s.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms_events = s.step_timed(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, ms_events
+
+
+def run_c1(L, W, steps, warmup):
+    import numpy as np
+    p = L.make_params(lattice=9, precision=4, nx=2048, ny=2048, T_ratio=0.75,
+                      sigma=W.SIGMA[("cs", 0.75, 9)], tau=1.0)
+    data = W.c1_porous(p.rho_g, p.rho_l)
+    solid = data["solid"]
+    s, nw = setup_solver(L, W, p, data, int(solid.sum()))
+    rc, d0 = s.diagnostics()
+    wall, ms = time_steps(s, warmup, steps)
+    rc, d1 = s.diagnostics()
+    if rc != 0:
+        raise RuntimeError("C1 run left the psi domain")
+    N = 2048 * 2048
+    nf = int((solid == 0).sum())
+    s.close()
+    return dict(N=N, n_fluid=nf, n_wall=nw, wall=wall, ms_events=ms,
+                mass_drift=abs(d1["mass"] - d0["mass"]) / d0["mass"], max_u=d1["max_u"],
+                rho=(d1["rho_min"], d1["rho_max"]), data=data, params=p)
+
+
+def run_c2(L, W, steps, warmup):
+    p = L.make_params(lattice=19, precision=4, nx=256, ny=256, nz=256, T_ratio=0.8,
+                      sigma=W.SIGMA[("cs", 0.8, 19)], tau=1.0)
+    data = W.c2_sphere(p.rho_g, p.rho_l)
+    solid = data["solid"]
+    s, nw = setup_solver(L, W, p, data, int(solid.sum()))
+    wall, ms = time_steps(s, warmup, steps)
+    rc, d1 = s.diagnostics()
+    if rc != 0:
+        raise RuntimeError("C2 run left the psi domain")
+    N = 256 ** 3
+    nf = int((solid == 0).sum())
+    s.close()
+    return dict(N=N, n_fluid=nf, n_wall=nw, wall=wall, ms_events=ms)
+
+
+def cpu_baseline(data, lbm_params, steps):
+    """The CPU oracle (FP64) on the same 2048^2 lattice and initial state,
+    `steps` steps."""
+    import numpy as np
+    import oracle as O
+    op = O.make_params(lattice=9, nx=2048, ny=2048, tau=1.0, T=lbm_params.eos_T,
+                       sigma=lbm_params.sigma, rho_g=lbm_params.rho_g, rho_l=lbm_params.rho_l)
+    solid = data["solid"]
+    walls = O.wall_nodes(op, solid)
+    phi = data["phi"].ravel()[walls]
+    drho = data["drho"].ravel()[walls]
+    f0 = O.init_eq(op, solid, data["rho"])
+    t0 = time.perf_counter()
+    O.run(op, solid, f0, steps, phi, drho)
+    dt = time.perf_counter() - t0
+    N = 2048 * 2048
+    return dict(value=N * steps / dt / 1e6, unit="MLUPS", cores=O.get_threads(), kind="oracle",
+                sample=f"D2Q9 2048x2048 porous workload, same initial state, {steps} FP64 "
+                       f"oracle steps ({dt:.1f} s)")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--c2-steps", type=int, default=500)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the step is measured on one device "
+              "(multi-GPU domain decomposition is not part of this library)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1908_04443_amd import lbm as L
+    from paper_1908_04443_amd import workloads as W
+    if not os.path.exists(L.LIB_PATH):
+        from paper_1908_04443_amd import build
+        build.build()
+    L.lib()
+    torch.cuda.init()
+
+    log(f"C1: D2Q9 2048^2 FP32 porous workload, warmup {args.warmup}, steps {args.steps}")
+    c1 = run_c1(L, W, args.steps, args.warmup)
+    N, nf = c1["N"], c1["n_fluid"]
+    ms_step = 1e3 * c1["wall"] / args.steps
+    mlups = N * args.steps / c1["wall"] / 1e6
+    kern_s = c1["ms_events"] / 1e3 / args.steps
+    b_alg = 2 * 9 * 4 * nf  # one read + one write of every fluid population
+    achieved = b_alg / kern_s / 1e9
+    traffic = measured_traffic("k_step_d2q9", "c1")
+    log(f"C1: {mlups:.1f} MLUPS, {achieved:.0f} GB/s algorithmic, "
+        f"mass drift {c1['mass_drift']:.2e}, max|u| {c1['max_u']:.3e}")
+
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "D2Q9 MRT pseudopotential 2048x2048 FP32, 400-cylinder "
+                               "porous medium, improved virtual density, CS 0.75 Tc",
+                   "nx": 2048, "ny": 2048, "lattice": "D2Q9", "fluid_nodes": nf,
+                   "wall_nodes": c1["n_wall"]},
+        "mflups": round(nf * args.steps / c1["wall"] / 1e6, 2),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
+                     "kernel": "k_step_d2q9", "bytes_per_launch_alg": b_alg,
+                     "kernel_ms": round(kern_s * 1e3, 5)},
+        "check": {"mass_rel_drift": c1["mass_drift"], "max_u": c1["max_u"],
+                  "rho_min_max": c1["rho"]},
+    }
+
+    if not args.no_secondary:
+        log(f"C2: D3Q19 256^3 FP32 sphere, {args.c2_steps} steps")
+        c2 = run_c2(L, W, args.c2_steps, 20)
+        k2 = c2["ms_events"] / 1e3 / args.c2_steps
+        b2 = 2 * 19 * 4 * c2["n_fluid"]
+        out["secondary"] = {
+            "d3q19_256cubed_fp32": {
+                "mlups": round(c2["N"] * args.c2_steps / c2["wall"] / 1e6, 2),
+                "achieved_GBs": round(b2 / k2 / 1e9, 1),
+                "frac": round(b2 / k2 / 1e9 / HBM_PEAK_GBS, 4),
+                "kernel_ms": round(k2 * 1e3, 5), "steps": args.c2_steps,
+                "traffic": measured_traffic("k_step_march", "c2")},
+        }
+        log(f"C2: {out['secondary']['d3q19_256cubed_fp32']}")
+
+    if not args.no_cpu_baseline:
+        log(f"CPU oracle: {args.cpu_steps} steps of the 2048^2 workload")
+        out["cpu_baseline"] = cpu_baseline(c1["data"], c1["params"], args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -66,7 +66,10 @@ enum { LBM_WET_IVD = 0, LBM_WET_VD = 1, LBM_WET_SFI = 2 };
  *              order is that of the relaxation matrix of Eq. 2: D2Q9
  *              (rho, e, eps, jx, qx, jy, qy, pxx, pxy); D3Q19 (rho, e, eps,
  *              jx, qx, jy, qy, jz, qz, 3pxx, 3pixx, pww, piww, pxy, pyz,
- *              pxz, mx, my, mz).  nu = (tau_nu - 0.5)/3.
+ *              pxz, mx, my, mz).  nu = (tau_nu - 0.5)/3.  Rows of one
+ *              moment group share one rate (isotropy): jx=jy(=jz),
+ *              qx=qy(=qz), pxx=pxy (2-D) / 3pxx=pww=pxy=pyz=pxz (3-D),
+ *              3pixx=piww, mx=my=mz; a vector that breaks this is rejected.
  *  eos         LBM_EOS_CS: p = rho R T (1+h+h^2-h^3)/(1-h)^3 - a rho^2,
  *              h = b rho / 4 (Carnahan-Starling).  LBM_EOS_PR: Eq. 18 with
  *              acentric factor eos_omega and Tc = (0.0778/0.45724)(a/b)/R.
@@ -109,8 +112,8 @@ const char* lbm_last_error(void);
 
 /* Host-only check of a parameter set (no device needed).  Returns
  * LBM_EINVAL with a message for: lattice not 9/19, precision not 4/8, a
- * non-positive size, nz != 1 for D2Q9, tau <= 0.5, non-positive EOS
- * constants, rho_g >= rho_l or rho_g <= 0. */
+ * non-positive size, nz != 1 for D2Q9, tau <= 0.5, unequal tau within a
+ * moment group, non-positive EOS constants, rho_g >= rho_l or rho_g <= 0. */
 int lbm_validate_params(const lbm_params* p);
 
 /* ------------------------------------------------------- thermodynamics */
@@ -198,6 +201,25 @@ int lbm_get_diagnostics(lbm_ctx* ctx, lbm_diag* host_out);
  * context stream right before the first and after the last step launch;
  * ms_total receives the elapsed time of the nsteps launches. */
 int lbm_step_timed(lbm_ctx* ctx, int64_t nsteps, double* ms_total);
+
+/* ------------------------------------------------------------ tuning */
+/* The step kernel exists in several tile shapes (and workgroup orderings).
+ * Number of variants for a lattice/precision; LBM_EINVAL if unknown. */
+int lbm_variant_count(int32_t lattice, int32_t precision);
+int lbm_set_variant(lbm_ctx* ctx, int32_t variant);
+int lbm_get_variant(lbm_ctx* ctx, int32_t* variant);
+
+/* Autotuner: times `steps` steps of every variant on the current problem
+ * (HIP events on the context stream, after 2 warm-up steps each) and keeps
+ * the fastest.  save_dev: device buffer of Q*N reals used to save and
+ * restore the state, so that tuning leaves the fields unchanged; with NULL
+ * the state advances by nvariants*(steps+2) steps.  ms_per_variant (host,
+ * nullable, lbm_variant_count entries) receives the mean step time of each.
+ * If the environment variable LBM_AUTOTUNE_CACHE names a file, a cached
+ * choice for the same lattice, precision and size is used without timing
+ * (unless ms_per_variant is requested), and new results are appended. */
+int lbm_autotune(lbm_ctx* ctx, int64_t steps, void* save_dev, int32_t* best_out,
+                 double* ms_per_variant);
 
 #ifdef __cplusplus
 }

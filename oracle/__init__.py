@@ -69,6 +69,7 @@ def lib():
                                   C.POINTER(C.c_int32)]
         L.orc_source.argtypes = [P, dp, dp, dp, C.c_double, dp]
         L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_get_threads.restype = C.c_int
         _lib = L
     return _lib
 
@@ -265,3 +266,7 @@ def state_tangent_cs(p, solid, f0, df0, nsteps, phi=None, drho=None, h=1e-30):
 
 def set_threads(n):
     lib().orc_set_threads(int(n))
+
+
+def get_threads():
+    return lib().orc_get_threads()

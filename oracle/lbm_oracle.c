@@ -688,3 +688,14 @@ int orc_state_tangent_cs(const orc_params* p, const uint8_t* solid,
     return rc;
 }
 #endif
+
+#ifndef ORC_COMPLEX
+int orc_get_threads(void) {
+#ifdef _OPENMP
+    extern int omp_get_max_threads(void);
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+#endif

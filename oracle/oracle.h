@@ -90,6 +90,7 @@ int orc_lattice(int32_t lattice, int32_t* e /* [Q][3] */, double* t, double* w,
 int orc_source(const orc_params* p, const double* u, const double* F,
                const double* Fm, double psi, double* S);
 void orc_set_threads(int n);
+int orc_get_threads(void);
 
 #ifdef __cplusplus
 }

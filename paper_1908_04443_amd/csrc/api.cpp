@@ -4,6 +4,7 @@
 // geometry upload and stream-ordered kernel launches.  No device memory is
 // allocated here; every device array is carved from the caller's workspace.
 #include <cmath>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -14,6 +15,10 @@
 namespace lbm {
 
 static thread_local std::string g_err;
+
+// relaxation group of each moment row (same tables as the device side)
+static const int kGroup9[9] = {0, 1, 2, 3, 4, 3, 4, 5, 5};
+static const int kGroup19[19] = {0, 1, 2, 3, 4, 3, 4, 3, 4, 5, 6, 5, 6, 5, 5, 5, 7, 7, 7};
 
 int fail(int code, const std::string& msg) {
     g_err = msg;
@@ -31,6 +36,15 @@ int validate(const lbm_params* p) {
     if (N > 4.0e9) return fail(LBM_EINVAL, "lattice too large");
     for (int k = 0; k < p->lattice; ++k)
         if (!(p->tau[k] > 0.5)) return fail(LBM_EINVAL, "every tau must exceed 0.5");
+    {
+        // rows of one moment group (e.g. jx, jy; pxx, pxy) share one rate
+        const int* grp = (p->lattice == 9) ? kGroup9 : kGroup19;
+        for (int k = 0; k < p->lattice; ++k)
+            for (int j = 0; j < k; ++j)
+                if (grp[j] == grp[k] && p->tau[j] != p->tau[k])
+                    return fail(LBM_EINVAL, "tau must be equal within a moment group (rows " +
+                                                std::to_string(j) + " and " + std::to_string(k) + ")");
+    }
     if (p->eos != LBM_EOS_CS && p->eos != LBM_EOS_PR) return fail(LBM_EINVAL, "unknown eos");
     if (!(p->eos_a > 0 && p->eos_b > 0 && p->eos_R > 0 && p->eos_T > 0))
         return fail(LBM_EINVAL, "EOS constants must be positive");
@@ -63,11 +77,9 @@ static Coef<real> make_coef(const lbm_ctx* c) {
     if (c->scheme == LBM_WET_SFI) C.G_w = (real)c->scalar;
     C.rho_g = (real)p.rho_g;
     C.rho_l = (real)p.rho_l;
-    for (int k = 0; k < 19; ++k) {
-        const double s = (k < p.lattice) ? 1.0 / p.tau[k] : 1.0;
-        C.s[k] = (real)s;
-        C.hs[k] = (real)(1.0 - 0.5 * s);
-    }
+    const int* grp = (p.lattice == 9) ? kGroup9 : kGroup19;
+    for (int g = 0; g < NGRP; ++g) C.s[g] = (real)1;
+    for (int k = 0; k < p.lattice; ++k) C.s[grp[k]] = (real)(1.0 / p.tau[k]);
     if (p.lattice == 9) {
         C.sig_e = (real)(12.0 * p.sigma / (p.tau[1] - 0.5));
         C.sig_eps = (real)(12.0 * p.sigma / (p.tau[2] - 0.5));
@@ -92,11 +104,18 @@ static Fields<real> make_fields(const lbm_ctx* c, int src) {
     return F;
 }
 
+// number of workgroups of the field/diagnostic launch (variant 0)
 static int grid_blocks(const lbm_params& p) {
     if (p.lattice == 9)
-        return p.precision == 4 ? grid2d_blocks<float>(p.nx, p.ny) : grid2d_blocks<double>(p.nx, p.ny);
-    return p.precision == 4 ? grid3d_blocks<float>(p.nx, p.ny, p.nz)
-                            : grid3d_blocks<double>(p.nx, p.ny, p.nz);
+        return p.precision == 4 ? grid2d_blocks<float>(p.nx, p.ny, 0)
+                                : grid2d_blocks<double>(p.nx, p.ny, 0);
+    return p.precision == 4 ? grid3d_blocks<float>(p.nx, p.ny, p.nz, 0)
+                            : grid3d_blocks<double>(p.nx, p.ny, p.nz, 0);
+}
+
+static int variant_count(int lattice, int precision) {
+    if (lattice == 9) return precision == 4 ? step2d_variants<float>() : step2d_variants<double>();
+    return precision == 4 ? step3d_variants<float>() : step3d_variants<double>();
 }
 
 // lay out the workspace; with ctx == nullptr only the size is computed
@@ -138,8 +157,8 @@ static int launch_mode(lbm_ctx* c, int mode, real* rho, real* u, double* part) {
     Coef<real> C = make_coef<real>(c);
     Fields<real> F = make_fields<real>(c, c->cur);
     FieldOut<real> O{rho, u, part};
-    hipError_t e = (c->p.lattice == 9) ? launch_step2d<real>(C, F, O, mode, c->stream)
-                                       : launch_step3d<real>(C, F, O, mode, c->stream);
+    hipError_t e = (c->p.lattice == 9) ? launch_step2d<real>(C, F, O, mode, 0, c->stream)
+                                       : launch_step3d<real>(C, F, O, mode, 0, c->stream);
     if (e != hipSuccess) return fail(LBM_EDEVICE, std::string("step launch: ") + hipGetErrorString(e));
     return LBM_OK;
 }
@@ -150,8 +169,9 @@ static int run_steps(lbm_ctx* c, int64_t nsteps) {
     FieldOut<real> O{nullptr, nullptr, nullptr};
     for (int64_t i = 0; i < nsteps; ++i) {
         Fields<real> F = make_fields<real>(c, c->cur);
-        hipError_t e = (c->p.lattice == 9) ? launch_step2d<real>(C, F, O, MODE_STEP, c->stream)
-                                           : launch_step3d<real>(C, F, O, MODE_STEP, c->stream);
+        hipError_t e = (c->p.lattice == 9)
+                           ? launch_step2d<real>(C, F, O, MODE_STEP, c->variant, c->stream)
+                           : launch_step3d<real>(C, F, O, MODE_STEP, c->variant, c->stream);
         if (e != hipSuccess)
             return fail(LBM_EDEVICE, std::string("step launch: ") + hipGetErrorString(e));
         c->cur ^= 1;
@@ -436,6 +456,100 @@ int lbm_get_diagnostics(lbm_ctx* c, lbm_diag* out) {
     if (flag[0]) {
         c->domain_error = true;
         return fail(LBM_EDOMAIN, "psi argument became negative or NaN");
+    }
+    return LBM_OK;
+}
+
+int lbm_variant_count(int32_t lattice, int32_t precision) {
+    if ((lattice != 9 && lattice != 19) || (precision != 4 && precision != 8))
+        return fail(LBM_EINVAL, "lattice must be 9/19 and precision 4/8");
+    return variant_count(lattice, precision);
+}
+
+int lbm_set_variant(lbm_ctx* c, int32_t variant) {
+    if (!c) return fail(LBM_EINVAL, "NULL context");
+    if (variant < 0 || variant >= variant_count(c->p.lattice, c->p.precision))
+        return fail(LBM_EINVAL, "variant out of range");
+    c->variant = variant;
+    return LBM_OK;
+}
+
+int lbm_get_variant(lbm_ctx* c, int32_t* variant) {
+    if (!c || !variant) return fail(LBM_EINVAL, "NULL argument");
+    *variant = c->variant;
+    return LBM_OK;
+}
+
+int lbm_autotune(lbm_ctx* c, int64_t steps, void* save_dev, int32_t* best_out,
+                 double* ms_per_variant) {
+    if (!c) return fail(LBM_EINVAL, "NULL context");
+    if (steps < 1) return fail(LBM_EINVAL, "steps must be >= 1");
+    if (!c->have_geom || !c->have_fields) return fail(LBM_ESTATE, "geometry and fields must be set");
+    if (c->domain_error) return fail(LBM_EDOMAIN, "a previous step left the psi domain");
+    const int nv = variant_count(c->p.lattice, c->p.precision);
+    const size_t fbytes = (size_t)c->Q * c->N * c->prec;
+    const char* cache = std::getenv("LBM_AUTOTUNE_CACHE");
+    char key[160];
+    std::snprintf(key, sizeof key, "lattice=%d precision=%d nx=%d ny=%d nz=%d", c->p.lattice,
+                  c->p.precision, c->p.nx, c->p.ny, c->p.nz);
+    if (cache && !ms_per_variant) {
+        if (FILE* fp = std::fopen(cache, "r")) {
+            char line[256];
+            int found = -1;
+            while (std::fgets(line, sizeof line, fp)) {
+                if (std::strncmp(line, key, std::strlen(key)) == 0) {
+                    const char* v = std::strstr(line, "variant=");
+                    if (v) found = std::atoi(v + 8);
+                }
+            }
+            std::fclose(fp);
+            if (found >= 0 && found < nv) {
+                c->variant = found;
+                if (best_out) *best_out = found;
+                return LBM_OK;
+            }
+        }
+    }
+    if (save_dev)
+        LBM_HIP(hipMemcpyAsync(save_dev, c->f[c->cur], fbytes, hipMemcpyDeviceToDevice, c->stream));
+    const int keep = c->variant;
+    int best = 0;
+    double best_ms = 1e300;
+    for (int v = 0; v < nv; ++v) {
+        c->variant = v;
+        int rc = c->prec == 4 ? run_steps<float>(c, 2) : run_steps<double>(c, 2);
+        if (rc != LBM_OK) {
+            c->variant = keep;
+            return rc;
+        }
+        LBM_HIP(hipEventRecord(c->ev0, c->stream));
+        rc = c->prec == 4 ? run_steps<float>(c, steps) : run_steps<double>(c, steps);
+        if (rc != LBM_OK) {
+            c->variant = keep;
+            return rc;
+        }
+        LBM_HIP(hipEventRecord(c->ev1, c->stream));
+        LBM_HIP(hipEventSynchronize(c->ev1));
+        float ms = 0.f;
+        LBM_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+        const double per = ms / (double)steps;
+        if (ms_per_variant) ms_per_variant[v] = per;
+        if (per < best_ms) {
+            best_ms = per;
+            best = v;
+        }
+    }
+    if (save_dev) {
+        LBM_HIP(hipMemcpyAsync(c->f[c->cur], save_dev, fbytes, hipMemcpyDeviceToDevice, c->stream));
+        LBM_HIP(hipStreamSynchronize(c->stream));
+    }
+    c->variant = best;
+    if (best_out) *best_out = best;
+    if (cache) {
+        if (FILE* fp = std::fopen(cache, "a")) {
+            std::fprintf(fp, "%s variant=%d ms=%.6f\n", key, best, best_ms);
+            std::fclose(fp);
+        }
     }
     return LBM_OK;
 }

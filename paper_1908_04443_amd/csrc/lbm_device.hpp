@@ -46,6 +46,8 @@ struct D2Q9 {
         {0, 0, 0, 0, 0, 1, -1, 1, -1}};
     // squared norms of the rows: M^-1 = M^T diag(1/norm)
     static constexpr int norm[9] = {9, 36, 36, 6, 12, 6, 12, 4, 4};
+    // relaxation group of each row (GRP_* below)
+    static constexpr int grp[9] = {0, 1, 2, 3, 4, 3, 4, 5, 5};
 };
 
 // ----------------------------------------------------------------- D3Q19
@@ -78,7 +80,13 @@ struct D3Q19 {
         {0, 0, 0, 0, 0, 0, 0, -1, 1, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1},
         {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, -1, -1, 1, -1, 1, 1, -1}};
     static constexpr int norm[19] = {19, 2394, 252, 10, 40, 10, 40, 10, 40, 36, 72, 12, 24, 4, 4, 4, 8, 8, 8};
+    static constexpr int grp[19] = {0, 1, 2, 3, 4, 3, 4, 3, 4, 5, 6, 5, 6, 5, 5, 5, 7, 7, 7};
 };
+
+// Moment groups that share one relaxation rate (isotropy): density, energy,
+// energy square, momentum, energy flux, viscous stress, its 4th-order
+// companion (3-D), and the 3rd-order moments m_x,y,z (3-D).
+enum { GRP_RHO = 0, GRP_E, GRP_EPS, GRP_J, GRP_Q, GRP_NU, GRP_PI, GRP_M, NGRP };
 
 // --------------------------------------------------------- argument block
 // Everything a step needs besides the population buffers.  Built on the
@@ -97,8 +105,7 @@ struct Coef {
     real psi_w;     // psi(rho_w) for VD
     real G_w;       // SFI adhesion strength
     real rho_g, rho_l;
-    real s[19];     // 1/tau per moment row
-    real hs[19];    // 1 - s/2 per moment row
+    real s[NGRP];   // 1/tau per moment group
     real sig_e;     // 12 sigma / (tau_e - 1/2)  (3-D: 114 sigma / (tau_e - 1/2))
     real sig_eps;   // 12 sigma / (tau_eps - 1/2) (3-D: 0)
     real body[3];
@@ -113,6 +120,73 @@ struct Fields {
     const real* phi;       // per wall node (IVD)
     const real* drho;      // per wall node (IVD)
     int32_t* flag;         // set to 1 when a psi argument is < 0 or NaN
+};
+
+// Workgroups are handed to the 8 XCDs of the chip round-robin by linear id.
+// Remapping the id so that XCD x receives one contiguous range of tiles
+// keeps the halo re-reads and the streaming writes that cross a tile edge
+// inside one L2.  Bijective for any nb.
+__device__ __forceinline__ int remap_xcd(int b, int nb) {
+    constexpr int NXCD = 8;
+    const int q = nb / NXCD, r = nb % NXCD;
+    const int x = b % NXCD, k = b / NXCD;
+    return (x < r) ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
+// Population arrays are addressed through a buffer resource when the whole
+// array is below 4 GiB: every direction of a node uses the same 32-bit
+// per-lane byte offset (the node) and a scalar offset a*N*sizeof(real) (the
+// direction), which is how CDNA addresses many arrays that share one index
+// without a 64-bit address per access.  The resource's range check makes an
+// out-of-range access read 0 and drop the write.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t nbytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)nbytes,
+                                             0x00020000);
+}
+
+template <typename real>
+__device__ __forceinline__ real buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    if constexpr (sizeof(real) == 4)
+        return __builtin_bit_cast(real, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+    else
+        return __builtin_bit_cast(real, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+
+template <typename real>
+__device__ __forceinline__ void buf_st(real v, __amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                       uint32_t soff) {
+    if constexpr (sizeof(real) == 4)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, (int)soff, 0);
+    else
+    {
+        typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)voff, (int)soff, 0);
+    }
+}
+
+// Read / write population a of node n (element index), through the buffer
+// resource (BUF) or plain 64-bit addressing.
+template <typename real, bool BUF>
+struct PopIO {
+    const real* fin;
+    real* fout;
+    uint32_t N;  // nodes
+    __amdgpu_buffer_rsrc_t rin, rout;
+    __device__ __forceinline__ PopIO(const real* i, real* o, uint32_t n, int Q) : fin(i), fout(o), N(n) {
+        if constexpr (BUF) {
+            const uint32_t bytes = (uint32_t)((uint64_t)Q * n * sizeof(real));
+            rin = make_rsrc(i, bytes);
+            rout = make_rsrc(o, bytes);
+        }
+    }
+    __device__ __forceinline__ real ld(int a, uint32_t n) const {
+        if constexpr (BUF) return buf_ld<real>(rin, n * (uint32_t)sizeof(real), (uint32_t)a * N * (uint32_t)sizeof(real));
+        else return fin[(size_t)a * N + n];
+    }
+    __device__ __forceinline__ void st(int a, uint32_t n, real v) const {
+        if constexpr (BUF) buf_st<real>(v, rout, n * (uint32_t)sizeof(real), (uint32_t)a * N * (uint32_t)sizeof(real));
+        else fout[(size_t)a * N + n] = v;
+    }
 };
 
 __device__ __forceinline__ int wrapi(int v, int n) {
@@ -148,10 +222,80 @@ __device__ __forceinline__ real psi_of(const Coef<real>& C, real rho, bool& bad)
 }
 
 // ---------------------------------------------------------- MRT collision
+// Equilibrium moments m_eq = M f_eq of the second-order equilibrium, row k.
+// D2Q9: rho (1, -2 + 3u^2, 1 - 3u^2, ux, -ux, uy, -uy, ux^2 - uy^2, ux uy).
+// D3Q19: e_eq = rho(-11 + 19 u^2), eps_eq = rho(3 - 5.5 u^2), q_eq =
+// -2/3 j, 3p_xx = rho(2ux^2 - uy^2 - uz^2), p_ww = rho(uy^2 - uz^2),
+// pi rows = -1/2 of their p rows, 3rd-order rows 0.
+template <typename L, typename real>
+__device__ __forceinline__ real meq_row(int k, real rho, const real* u, real u2) {
+    if constexpr (L::Q == 9) {
+        switch (k) {
+        case 1: return rho * (real(-2) + real(3) * u2);
+        case 2: return rho * (real(1) - real(3) * u2);
+        case 4: return -rho * u[0];
+        case 6: return -rho * u[1];
+        case 7: return rho * (u[0] * u[0] - u[1] * u[1]);
+        default: return rho * u[0] * u[1];  // k == 8
+        }
+    } else {
+        switch (k) {
+        case 1: return rho * (real(-11) + real(19) * u2);
+        case 2: return rho * (real(3) - real(5.5) * u2);
+        case 4: return real(-2.0 / 3.0) * rho * u[0];
+        case 6: return real(-2.0 / 3.0) * rho * u[1];
+        case 8: return real(-2.0 / 3.0) * rho * u[2];
+        case 9: return rho * (real(2) * u[0] * u[0] - u[1] * u[1] - u[2] * u[2]);
+        case 10: return real(-0.5) * rho * (real(2) * u[0] * u[0] - u[1] * u[1] - u[2] * u[2]);
+        case 11: return rho * (u[1] * u[1] - u[2] * u[2]);
+        case 12: return real(-0.5) * rho * (u[1] * u[1] - u[2] * u[2]);
+        case 13: return rho * u[0] * u[1];
+        case 14: return rho * u[1] * u[2];
+        case 15: return rho * u[0] * u[2];
+        default: return real(0);  // 16, 17, 18
+        }
+    }
+}
+
+// Moment-space forcing, row k.  D2Q9: Eq. 7, with the thermodynamic-
+// consistency term sig = |F_m|^2 / psi^2 on the e and eps rows.  D3Q19:
+// M G of the Guo discrete force plus the same pressure shift on the e row.
+template <typename L, typename real>
+__device__ __forceinline__ real src_row(const Coef<real>& C, int k, const real* u, const real* F,
+                                        real uF, real sgm) {
+    if constexpr (L::Q == 9) {
+        switch (k) {
+        case 1: return real(6) * uF + C.sig_e * sgm;
+        case 2: return real(-6) * uF - C.sig_eps * sgm;
+        case 4: return -F[0];
+        case 6: return -F[1];
+        case 7: return real(2) * (u[0] * F[0] - u[1] * F[1]);
+        default: return u[0] * F[1] + u[1] * F[0];  // k == 8
+        }
+    } else {
+        switch (k) {
+        case 1: return real(38) * uF + C.sig_e * sgm;
+        case 2: return real(-11) * uF;
+        case 4: return real(-2.0 / 3.0) * F[0];
+        case 6: return real(-2.0 / 3.0) * F[1];
+        case 8: return real(-2.0 / 3.0) * F[2];
+        case 9: return real(2) * (real(2) * u[0] * F[0] - u[1] * F[1] - u[2] * F[2]);
+        case 10: return -(real(2) * u[0] * F[0] - u[1] * F[1] - u[2] * F[2]);
+        case 11: return real(2) * (u[1] * F[1] - u[2] * F[2]);
+        case 12: return -(u[1] * F[1] - u[2] * F[2]);
+        case 13: return u[0] * F[1] + u[1] * F[0];
+        case 14: return u[1] * F[2] + u[2] * F[1];
+        case 15: return u[0] * F[2] + u[2] * F[0];
+        default: return real(0);
+        }
+    }
+}
+
 // Post-collision populations of one fluid node (Eq. 2, forcing of Eq. 7):
 // m = M f, m* = m - S (m - m_eq) + (I - S/2) Src, f* = M^-1 m*.
-// in: f (populations), rho, j = sum e f, F (total force), Fm (cohesive
-// force of Eq. 5), psi (own pseudopotential).  out: fs.  Also returns u.
+// in: f (populations), rho, F (total force), Fm (cohesive force of Eq. 5),
+// psi (own pseudopotential).  out: fs and u.  Each row's m_eq and source
+// are formed when the row is relaxed, which keeps few values live.
 template <typename L, typename real>
 __device__ __forceinline__ void collide(const Coef<real>& C, const real* f, real rho,
                                         const real* F, const real* Fm, real psi,
@@ -171,95 +315,38 @@ __device__ __forceinline__ void collide(const Coef<real>& C, const real* f, real
         }
         m[k] = s;
     }
-    const real inv_rho = real(1) / rho;
     real u[3], Fv[3];
     Fv[0] = F[0];
     Fv[1] = F[1];
     Fv[2] = (L::D == 3) ? F[2] : real(0);
-    u[0] = (m[3] + real(0.5) * Fv[0]) * inv_rho;
-    u[1] = (m[5] + real(0.5) * Fv[1]) * inv_rho;
-    u[2] = (L::D == 3) ? (m[7] + real(0.5) * Fv[2]) * inv_rho : real(0);
+    u[0] = (m[3] + real(0.5) * Fv[0]) / rho;
+    u[1] = (m[5] + real(0.5) * Fv[1]) / rho;
+    u[2] = (L::D == 3) ? (m[7] + real(0.5) * Fv[2]) / rho : real(0);
     u_out[0] = u[0];
     u_out[1] = u[1];
     if (L::D == 3) u_out[2] = u[2];
     const real uF = u[0] * Fv[0] + u[1] * Fv[1] + u[2] * Fv[2];
+    const real u2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     real fm2 = Fm[0] * Fm[0] + Fm[1] * Fm[1];
     if (L::D == 3) fm2 += Fm[2] * Fm[2];
     const real sgm = (psi > real(0)) ? fm2 / (psi * psi) : real(0);
-    real meq[Q], src[Q];
-    if constexpr (L::Q == 9) {
-        const real u2 = u[0] * u[0] + u[1] * u[1];
-        meq[0] = rho;
-        meq[1] = rho * (real(-2) + real(3) * u2);
-        meq[2] = rho * (real(1) - real(3) * u2);
-        meq[3] = rho * u[0];
-        meq[4] = -rho * u[0];
-        meq[5] = rho * u[1];
-        meq[6] = -rho * u[1];
-        meq[7] = rho * (u[0] * u[0] - u[1] * u[1]);
-        meq[8] = rho * u[0] * u[1];
-        src[0] = real(0);
-        src[1] = real(6) * uF + C.sig_e * sgm;
-        src[2] = real(-6) * uF - C.sig_eps * sgm;
-        src[3] = Fv[0];
-        src[4] = -Fv[0];
-        src[5] = Fv[1];
-        src[6] = -Fv[1];
-        src[7] = real(2) * (u[0] * Fv[0] - u[1] * Fv[1]);
-        src[8] = u[0] * Fv[1] + u[1] * Fv[0];
-    } else {
-        const real ux = u[0], uy = u[1], uz = u[2];
-        const real u2 = ux * ux + uy * uy + uz * uz;
-        const real pxx = real(2) * ux * ux - uy * uy - uz * uz;
-        const real pww = uy * uy - uz * uz;
-        meq[0] = rho;
-        meq[1] = rho * (real(-11) + real(19) * u2);
-        meq[2] = rho * (real(3) - real(5.5) * u2);
-        meq[3] = rho * ux;
-        meq[4] = real(-2.0 / 3.0) * rho * ux;
-        meq[5] = rho * uy;
-        meq[6] = real(-2.0 / 3.0) * rho * uy;
-        meq[7] = rho * uz;
-        meq[8] = real(-2.0 / 3.0) * rho * uz;
-        meq[9] = rho * pxx;
-        meq[10] = real(-0.5) * rho * pxx;
-        meq[11] = rho * pww;
-        meq[12] = real(-0.5) * rho * pww;
-        meq[13] = rho * ux * uy;
-        meq[14] = rho * uy * uz;
-        meq[15] = rho * ux * uz;
-        meq[16] = real(0);
-        meq[17] = real(0);
-        meq[18] = real(0);
-        const real Fx = Fv[0], Fy = Fv[1], Fz = Fv[2];
-        const real sxx = real(2) * ux * Fx - uy * Fy - uz * Fz;
-        const real sww = uy * Fy - uz * Fz;
-        src[0] = real(0);
-        src[1] = real(38) * uF + C.sig_e * sgm;
-        src[2] = real(-11) * uF;
-        src[3] = Fx;
-        src[4] = real(-2.0 / 3.0) * Fx;
-        src[5] = Fy;
-        src[6] = real(-2.0 / 3.0) * Fy;
-        src[7] = Fz;
-        src[8] = real(-2.0 / 3.0) * Fz;
-        src[9] = real(2) * sxx;
-        src[10] = -sxx;
-        src[11] = real(2) * sww;
-        src[12] = -sww;
-        src[13] = ux * Fy + uy * Fx;
-        src[14] = uy * Fz + uz * Fy;
-        src[15] = ux * Fz + uz * Fx;
-        src[16] = real(0);
-        src[17] = real(0);
-        src[18] = real(0);
-    }
-    // relax in moment space, scale by the inverse row norms
-    real ms[Q];
+    // Conserved rows: density keeps its value (S_0 = 0, m_eq = rho) and the
+    // momentum rows give j + F for any relaxation rate, since
+    // j - j_eq = -F/2.  All other rows relax with their group's rate.
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
-        real mk = m[k] - C.s[k] * (m[k] - meq[k]) + C.hs[k] * src[k];
-        ms[k] = mk * real(1.0 / L::norm[k]);
+        real mk;
+        if (k == 0) mk = m[0];
+        else if (k == 3) mk = m[3] + Fv[0];
+        else if (k == 5) mk = m[5] + Fv[1];
+        else if (L::D == 3 && k == 7) mk = m[7] + Fv[2];
+        else {
+            const real sk = C.s[L::grp[k]];
+            const real me = meq_row<L, real>(k, rho, u, u2);
+            const real sr = src_row<L, real>(C, k, u, Fv, uF, sgm);
+            mk = m[k] - sk * (m[k] - me) + (real(1) - real(0.5) * sk) * sr;
+        }
+        m[k] = mk * real(1.0 / L::norm[k]);
     }
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
@@ -268,7 +355,7 @@ __device__ __forceinline__ void collide(const Coef<real>& C, const real* f, real
 #pragma unroll
         for (int k = 0; k < Q; ++k) {
             if (L::M[k][a] == 0) continue;
-            real term = (L::M[k][a] == 1) ? ms[k] : (L::M[k][a] == -1) ? -ms[k] : real(L::M[k][a]) * ms[k];
+            real term = (L::M[k][a] == 1) ? m[k] : (L::M[k][a] == -1) ? -m[k] : real(L::M[k][a]) * m[k];
             s = first ? term : s + term;
             first = false;
         }

@@ -87,6 +87,7 @@ struct lbm_ctx {
     lbm::Geometry geom;
     bool have_geom = false, have_fields = false, domain_error = false;
     int scheme = LBM_WET_IVD;
+    int variant = 0;  // step-kernel tile variant (autotuner choice)
     double scalar = 0.0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };

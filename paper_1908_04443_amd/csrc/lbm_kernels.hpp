@@ -69,16 +69,27 @@ __device__ __forceinline__ void block_reduce_diag(double sum, real umax, real rm
 }
 
 // fused steps
+// (variant: tile shape chosen by the autotuner; the field mode always uses
+// variant 0)
 template <typename real>
-int grid2d_blocks(int nx, int ny);
+int step2d_variants();
+template <typename real>
+int grid2d_blocks(int nx, int ny, int variant);
 template <typename real>
 hipError_t launch_step2d(const Coef<real>& C, const Fields<real>& F, const FieldOut<real>& O,
-                         int mode, hipStream_t s);
+                         int mode, int variant, hipStream_t s);
 template <typename real>
-int grid3d_blocks(int nx, int ny, int nz);
+int step2d_march_variants();
+template <typename real>
+hipError_t launch_step2d_march(const Coef<real>& C, const Fields<real>& F, const FieldOut<real>& O,
+                               int idx, hipStream_t s);
+template <typename real>
+int step3d_variants();
+template <typename real>
+int grid3d_blocks(int nx, int ny, int nz, int variant);
 template <typename real>
 hipError_t launch_step3d(const Coef<real>& C, const Fields<real>& F, const FieldOut<real>& O,
-                         int mode, hipStream_t s);
+                         int mode, int variant, hipStream_t s);
 
 // auxiliary kernels
 template <typename real>

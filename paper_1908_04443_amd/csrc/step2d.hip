@@ -12,9 +12,9 @@
 // rho on the tile plus a 2-node halo and psi (with the wall virtual
 // densities) on the tile plus a 1-node halo in LDS.  Halo populations are
 // re-read (they are served by L2 / Infinity Cache, not HBM, when adjacent
-// tiles run close in time); each owned node's populations are read once
-// into registers, so the HBM traffic stays close to one read and one write
-// of f per fluid node.
+// tiles run close in time on one XCD); each owned node's populations are
+// read once into registers, so the HBM traffic stays close to one read and
+// one write of f per fluid node.
 //
 // State: post-streaming populations, SoA f[a*N + n]; fin -> fout ping-pong.
 // Only fluid slots of fout are written; a population that would enter a
@@ -24,7 +24,7 @@
 
 namespace lbm {
 
-template <typename real, int TX, int TY, int NT, int MODE>
+template <typename real, int TX, int TY, int NT, int MODE, bool XCD, bool BUF>
 __global__ __launch_bounds__(NT) void k_step_d2q9(Coef<real> C, Fields<real> Fd,
                                                   FieldOut<real> Out) {
     using L = D2Q9;
@@ -37,18 +37,28 @@ __global__ __launch_bounds__(NT) void k_step_d2q9(Coef<real> C, Fields<real> Fd,
     __shared__ uint8_t s_cls[LX * LY];
     __shared__ real s_rho[LX * LY];
     __shared__ real s_psi[LX * LY];
+    __shared__ uint32_t s_col[LX];  // wrapped x of each halo column
+    __shared__ uint32_t s_row[LY];  // wrapped y * nx of each halo row
 
     const int nx = C.nx, ny = C.ny;
-    const size_t N = (size_t)nx * ny;
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+    const uint32_t N = (uint32_t)nx * (uint32_t)ny;
+    const PopIO<real, BUF> io(Fd.fin, Fd.fout, N, 9);
+    const int gxb = gridDim.x, nblk = gridDim.x * gridDim.y;
+    int bid = blockIdx.x + gxb * blockIdx.y;
+    if (XCD) bid = remap_xcd(bid, nblk);
+    const int x0 = (bid % gxb) * TX, y0 = (bid / gxb) * TY;
     const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
     bool bad = false;
 
+    for (int i = tid; i < LX + LY; i += NT) {
+        if (i < LX) s_col[i] = (uint32_t)wrapi(x0 - 2 + i, nx);
+        else s_row[i - LX] = (uint32_t)wrapi(y0 - 2 + (i - LX), ny) * (uint32_t)nx;
+    }
+    __syncthreads();
     // node classes of the tile + 2 halo
     for (int i = tid; i < LX * LY; i += NT) {
-        int lx = i % LX, ly = i / LX;
-        int gx = wrapi(x0 - 2 + lx, nx), gy = wrapi(y0 - 2 + ly, ny);
-        s_cls[i] = Fd.cls[(size_t)gy * nx + gx];
+        const int lx = i % LX, ly = i / LX;
+        s_cls[i] = Fd.cls[s_row[ly] + s_col[lx]];
     }
     __syncthreads();
 
@@ -58,11 +68,11 @@ __global__ __launch_bounds__(NT) void k_step_d2q9(Coef<real> C, Fields<real> Fd,
     for (int k = 0; k < RPT; ++k) {
         const int ly = ty + k * ROWS;
         const int p = (ly + 2) * LX + tx + 2;
-        const size_t n = (size_t)wrapi(y0 + ly, ny) * nx + wrapi(x0 + tx, nx);
+        const uint32_t n = s_row[ly + 2] + s_col[tx + 2];
         real r = real(0);
         if (s_cls[p] == CLS_FLUID) {
 #pragma unroll
-            for (int a = 0; a < 9; ++a) f[k][a] = Fd.fin[a * N + n];
+            for (int a = 0; a < 9; ++a) f[k][a] = io.ld(a, n);
             r = f[k][0];
 #pragma unroll
             for (int a = 1; a < 9; ++a) r += f[k][a];
@@ -91,10 +101,10 @@ __global__ __launch_bounds__(NT) void k_step_d2q9(Coef<real> C, Fields<real> Fd,
         const int p = ly * LX + lx;
         real r = real(0);
         if (s_cls[p] == CLS_FLUID) {
-            const size_t n = (size_t)wrapi(y0 - 2 + ly, ny) * nx + wrapi(x0 - 2 + lx, nx);
-            r = Fd.fin[n];
+            const uint32_t n = s_row[ly] + s_col[lx];
+            r = io.ld(0, n);
 #pragma unroll
-            for (int a = 1; a < 9; ++a) r += Fd.fin[a * N + n];
+            for (int a = 1; a < 9; ++a) r += io.ld(a, n);
         }
         s_rho[p] = r;
     }
@@ -124,8 +134,7 @@ __global__ __launch_bounds__(NT) void k_step_d2q9(Coef<real> C, Fields<real> Fd,
                     }
                 }
                 const real rave = num / den;
-                const size_t n = (size_t)wrapi(y0 - 2 + ly, ny) * nx + wrapi(x0 - 2 + lx, nx);
-                const int kw = Fd.widx[n];
+                const int kw = Fd.widx[s_row[ly] + s_col[lx]];
                 // Eq. 16 (phi scales, drho shifts) and the limiter
                 real rw = Fd.phi[kw] * rave - Fd.drho[kw];
                 rw = rw > C.rho_l ? C.rho_l : rw;
@@ -153,14 +162,14 @@ __global__ __launch_bounds__(NT) void k_step_d2q9(Coef<real> C, Fields<real> Fd,
         const int gx = x0 + tx, gy = y0 + ly;
         if (gx >= nx || gy >= ny) continue;  // ragged tile: not owned
         const int p = (ly + 2) * LX + tx + 2;
-        const size_t n = (size_t)gy * nx + gx;
+        const uint32_t n = s_row[ly + 2] + s_col[tx + 2];
         const uint8_t c = s_cls[p];
         if (c != CLS_FLUID) {
             if (MODE == MODE_FIELDS) {
                 if (Out.rho) Out.rho[n] = (c == CLS_WALL) ? s_rho[p] : real(0);
                 if (Out.u) {
                     Out.u[n] = real(0);
-                    Out.u[N + n] = real(0);
+                    Out.u[(size_t)N + n] = real(0);
                 }
             }
             continue;
@@ -201,7 +210,7 @@ __global__ __launch_bounds__(NT) void k_step_d2q9(Coef<real> C, Fields<real> Fd,
             if (Out.rho) Out.rho[n] = rho;
             if (Out.u) {
                 Out.u[n] = ux;
-                Out.u[N + n] = uy;
+                Out.u[(size_t)N + n] = uy;
             }
             const real um = sqrt(ux * ux + uy * uy);
             d_sum += (double)rho;
@@ -219,60 +228,113 @@ __global__ __launch_bounds__(NT) void k_step_d2q9(Coef<real> C, Fields<real> Fd,
         for (int a = 0; a < 9; ++a) {
             const int q = p + L::ex[a] + L::ey[a] * LX;
             if (s_cls[q] == CLS_FLUID) {
-                int tx2 = gx + L::ex[a], ty2 = gy + L::ey[a];
-                tx2 = tx2 < 0 ? tx2 + nx : (tx2 >= nx ? tx2 - nx : tx2);
-                ty2 = ty2 < 0 ? ty2 + ny : (ty2 >= ny ? ty2 - ny : ty2);
-                Fd.fout[a * N + (size_t)ty2 * nx + tx2] = fs[a];
+                const uint32_t m = s_row[ly + 2 + L::ey[a]] + s_col[tx + 2 + L::ex[a]];
+                io.st(a, m, fs[a]);
             } else {
-                Fd.fout[L::opp[a] * N + n] = fs[a];
+                io.st(L::opp[a], n, fs[a]);
             }
         }
     }
 
     if (MODE == MODE_FIELDS && Out.part) {
-        block_reduce_diag<NT>(d_sum, d_umax, d_rmin, d_rmax, d_cnt,
-                              Out.part + 5 * (blockIdx.y * gridDim.x + blockIdx.x));
+        block_reduce_diag<NT>(d_sum, d_umax, d_rmin, d_rmax, d_cnt, Out.part + 5 * bid);
     }
     if (bad) Fd.flag[0] = 1;
 }
 
 // ----------------------------------------------------------------- launch
-template <typename real>
-struct Tile2D;
-template <>
-struct Tile2D<float> {
-    static constexpr int TX = 64, TY = 16, NT = 256;
-};
-template <>
-struct Tile2D<double> {
-    static constexpr int TX = 64, TY = 8, NT = 256;
+// Tile variants the autotuner chooses among (variant 0 is the default and
+// the shape used by the field/diagnostic mode).
+struct Shape2D {
+    int TX, TY, NT;
+    bool xcd;
 };
 
 template <typename real>
-int grid2d_blocks(int nx, int ny) {
-    using T = Tile2D<real>;
-    return ((nx + T::TX - 1) / T::TX) * ((ny + T::TY - 1) / T::TY);
+struct Variants2D;
+template <>
+struct Variants2D<float> {
+    static constexpr int count = 6;
+    static constexpr Shape2D shape[count] = {{64, 16, 256, true},  {64, 16, 256, false},
+                                             {128, 8, 256, true},  {64, 32, 256, true},
+                                             {256, 4, 256, true},  {128, 16, 256, true}};
+};
+template <>
+struct Variants2D<double> {
+    static constexpr int count = 3;
+    static constexpr Shape2D shape[count] = {{64, 8, 256, true}, {64, 8, 256, false},
+                                             {128, 4, 256, true}};
+};
+
+// variants beyond the tile shapes are the y-sweep kernel (step_march.hip)
+template <typename real>
+int step2d_variants() {
+    return Variants2D<real>::count + step2d_march_variants<real>();
+}
+
+template <typename real>
+int grid2d_blocks(int nx, int ny, int variant) {
+    const Shape2D s = Variants2D<real>::shape[variant < Variants2D<real>::count ? variant : 0];
+    return ((nx + s.TX - 1) / s.TX) * ((ny + s.TY - 1) / s.TY);
+}
+
+template <typename real, int V, int MODE, bool BUF = true>
+static void launch_v(const Coef<real>& C, const Fields<real>& F, const FieldOut<real>& O,
+                     hipStream_t s) {
+    constexpr Shape2D sh = Variants2D<real>::shape[V];
+    dim3 grid((C.nx + sh.TX - 1) / sh.TX, (C.ny + sh.TY - 1) / sh.TY);
+    hipLaunchKernelGGL((k_step_d2q9<real, sh.TX, sh.TY, sh.NT, MODE, sh.xcd, BUF>), grid,
+                       dim3(sh.NT), 0, s, C, F, O);
+}
+
+// population arrays of 4 GiB or more cannot use 32-bit buffer offsets
+template <typename real>
+static bool fits_buffer(const Coef<real>& C, int Q) {
+    return (uint64_t)Q * (uint64_t)C.nx * C.ny * C.nz * sizeof(real) <= 0xFFFFFFFFull;
+}
+
+template <typename real, int V>
+static void launch_mode(const Coef<real>& C, const Fields<real>& F, const FieldOut<real>& O,
+                        int mode, hipStream_t s) {
+    if (mode == MODE_STEP) launch_v<real, V, MODE_STEP>(C, F, O, s);
+    else launch_v<real, V, MODE_FIELDS>(C, F, O, s);
 }
 
 template <typename real>
 hipError_t launch_step2d(const Coef<real>& C, const Fields<real>& F, const FieldOut<real>& O,
-                         int mode, hipStream_t s) {
-    using T = Tile2D<real>;
-    dim3 grid((C.nx + T::TX - 1) / T::TX, (C.ny + T::TY - 1) / T::TY);
-    if (mode == MODE_STEP)
-        hipLaunchKernelGGL((k_step_d2q9<real, T::TX, T::TY, T::NT, MODE_STEP>), grid, dim3(T::NT),
-                           0, s, C, F, O);
-    else
-        hipLaunchKernelGGL((k_step_d2q9<real, T::TX, T::TY, T::NT, MODE_FIELDS>), grid,
-                           dim3(T::NT), 0, s, C, F, O);
+                         int mode, int variant, hipStream_t s) {
+    if (mode == MODE_FIELDS) variant = 0;
+    if (!fits_buffer(C, 9)) {
+        if (mode == MODE_STEP) launch_v<real, 0, MODE_STEP, false>(C, F, O, s);
+        else launch_v<real, 0, MODE_FIELDS, false>(C, F, O, s);
+        return hipGetLastError();
+    }
+    if (variant >= Variants2D<real>::count)
+        return launch_step2d_march<real>(C, F, O, variant - Variants2D<real>::count, s);
+    switch (variant) {
+    case 0: launch_mode<real, 0>(C, F, O, mode, s); break;
+    case 1: launch_mode<real, 1>(C, F, O, mode, s); break;
+    case 2: launch_mode<real, 2>(C, F, O, mode, s); break;
+    default:
+        if constexpr (Variants2D<real>::count > 3) {
+            if (variant == 3) launch_mode<real, 3>(C, F, O, mode, s);
+            else if (variant == 4) launch_mode<real, 4>(C, F, O, mode, s);
+            else if (variant == 5) launch_mode<real, 5>(C, F, O, mode, s);
+            else return hipErrorInvalidValue;
+        } else {
+            return hipErrorInvalidValue;
+        }
+    }
     return hipGetLastError();
 }
 
-template int grid2d_blocks<float>(int, int);
-template int grid2d_blocks<double>(int, int);
+template int step2d_variants<float>();
+template int step2d_variants<double>();
+template int grid2d_blocks<float>(int, int, int);
+template int grid2d_blocks<double>(int, int, int);
 template hipError_t launch_step2d<float>(const Coef<float>&, const Fields<float>&,
-                                         const FieldOut<float>&, int, hipStream_t);
+                                         const FieldOut<float>&, int, int, hipStream_t);
 template hipError_t launch_step2d<double>(const Coef<double>&, const Fields<double>&,
-                                          const FieldOut<double>&, int, hipStream_t);
+                                          const FieldOut<double>&, int, int, hipStream_t);
 
 }  // namespace lbm

@@ -8,20 +8,22 @@
 // slices along the sweep axis.  It walks the chunk plus two halo slices on
 // each side; for each slice it
 //   A  loads node classes and densities of the cross-section tile plus a
-//      2-node halo into slot (it mod 5) of an LDS ring; owned nodes keep
-//      their populations in a 3-deep register pipeline,
+//      2-node halo into slot (it mod 5) of an LDS ring,
 //   B  finishes the wall virtual densities and psi of the previous slice on
 //      the tile plus a 1-node halo (ring of 4 psi slots),
-//   C  collides and streams the slice two behind the load front.
-// Only the cross-section halo is re-read (from L2); along the sweep axis
-// each slice is read once per chunk, so the re-read fraction is
-// (TZ+4)/TZ * (ring / tile) instead of the cube of a 3-D halo.
+//   C  collides and streams the slice two behind the load front; its
+//      populations are read again here (two iterations after phase A read
+//      them, so they come from L2) instead of being held in registers,
+//      which keeps the register count low enough for several waves per SIMD.
+// Only the cross-section halo is re-read; along the sweep axis each slice
+// is read once per chunk, so the re-read fraction is (TZ+4)/TZ * (ring /
+// tile) instead of the cube of a 3-D halo.
 #include "lbm_device.hpp"
 #include "lbm_kernels.hpp"
 
 namespace lbm {
 
-template <typename L, typename real, int TX, int TY, int TZ, int MODE>
+template <typename L, typename real, int TX, int TY, int TZ, int MODE, bool XCD, bool BUF>
 __global__ __launch_bounds__(TX* TY) void k_step_march(Coef<real> C, Fields<real> Fd,
                                                        FieldOut<real> Out) {
     constexpr bool D3 = (L::D == 3);
@@ -40,10 +42,16 @@ __global__ __launch_bounds__(TX* TY) void k_step_march(Coef<real> C, Fields<real
     const int na = C.nx;
     const int nb = D3 ? C.ny : 1;
     const int nc = D3 ? C.nz : C.ny;
-    const size_t nab = (size_t)na * nb;
-    const size_t N = nab * nc;
+    const uint32_t nab = (uint32_t)na * (uint32_t)nb;
+    const uint32_t N = nab * (uint32_t)nc;
+    const PopIO<real, BUF> io(Fd.fin, Fd.fout, N, Q);
     const int tid = threadIdx.x;
-    const int a0 = blockIdx.x * TX, b0 = blockIdx.y * TY, c0 = blockIdx.z * TZ;
+    const int nblk = gridDim.x * gridDim.y * gridDim.z;
+    int bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    if (XCD) bid = remap_xcd(bid, nblk);
+    const int bx = bid % gridDim.x, by = (bid / gridDim.x) % gridDim.y;
+    const int bz = bid / (gridDim.x * gridDim.y);
+    const int a0 = bx * TX, b0 = by * TY, c0 = bz * TZ;
 
     // owned position of this thread and its halo position (if any)
     const int own_la = 2 + tid % TX, own_lb = HB + tid / TX;
@@ -73,15 +81,12 @@ __global__ __launch_bounds__(TX* TY) void k_step_march(Coef<real> C, Fields<real
     }
     const int own_a = a0 + own_la - 2, own_b = b0 + own_lb - HB;
     const bool own_in = own_a < na && own_b < nb;  // ragged tiles
-    const size_t own_ab = (size_t)wrapi(own_b, nb) * na + wrapi(own_a, na);
-    size_t ring_ab = 0;
-    if (tid < RING) ring_ab = (size_t)wrapi(b0 + ring_lb - HB, nb) * na + wrapi(a0 + ring_la - 2, na);
+    const uint32_t own_ab = (uint32_t)wrapi(own_b, nb) * na + wrapi(own_a, na);
+    uint32_t ring_ab = 0;
+    if (tid < RING) ring_ab = (uint32_t)wrapi(b0 + ring_lb - HB, nb) * na + wrapi(a0 + ring_la - 2, na);
     const int own_p = own_lb * PA + own_la;
     const int ring_p = (tid < RING) ? ring_lb * PA + ring_la : 0;
 
-    real f0[Q], f1[Q], f2[Q];  // populations of the slices it, it-1, it-2
-#pragma unroll
-    for (int a = 0; a < Q; ++a) f0[a] = f1[a] = f2[a] = real(0);
     bool bad = false;
     double d_sum = 0.0;
     real d_umax = real(0), d_rmin = real(1e30), d_rmax = real(-1e30);
@@ -92,25 +97,14 @@ __global__ __launch_bounds__(TX* TY) void k_step_march(Coef<real> C, Fields<real
         {
             const int slot = it % NSLOT;
             const int cz = wrapi(c0 - 2 + it, nc);
-            const size_t base = (size_t)cz * nab;
-            // shift the register pipeline
-#pragma unroll
-            for (int a = 0; a < Q; ++a) {
-                f2[a] = f1[a];
-                f1[a] = f0[a];
-            }
+            const uint32_t base = (uint32_t)cz * nab;
             const uint8_t co = Fd.cls[base + own_ab];
             s_cls[slot][own_p] = co;
             real r = real(0);
             if (co == CLS_FLUID) {
+                r = io.ld(0, base + own_ab);
 #pragma unroll
-                for (int a = 0; a < Q; ++a) f0[a] = Fd.fin[a * N + base + own_ab];
-                r = f0[0];
-#pragma unroll
-                for (int a = 1; a < Q; ++a) r += f0[a];
-            } else {
-#pragma unroll
-                for (int a = 0; a < Q; ++a) f0[a] = real(0);
+                for (int a = 1; a < Q; ++a) r += io.ld(a, base + own_ab);
             }
             s_rho[slot][own_p] = r;
             if (tid < RING) {
@@ -118,9 +112,9 @@ __global__ __launch_bounds__(TX* TY) void k_step_march(Coef<real> C, Fields<real
                 s_cls[slot][ring_p] = cr;
                 real rr = real(0);
                 if (cr == CLS_FLUID) {
-                    rr = Fd.fin[base + ring_ab];
+                    rr = io.ld(0, base + ring_ab);
 #pragma unroll
-                    for (int a = 1; a < Q; ++a) rr += Fd.fin[a * N + base + ring_ab];
+                    for (int a = 1; a < Q; ++a) rr += io.ld(a, base + ring_ab);
                 }
                 s_rho[slot][ring_p] = rr;
             }
@@ -159,8 +153,8 @@ __global__ __launch_bounds__(TX* TY) void k_step_march(Coef<real> C, Fields<real
                             }
                         }
                         const real rave = num / den;
-                        const size_t n = (size_t)cz * nab +
-                                         (size_t)wrapi(b0 + lb - HB, nb) * na + wrapi(a0 + la - 2, na);
+                        const uint32_t n = (uint32_t)cz * nab +
+                                           (uint32_t)wrapi(b0 + lb - HB, nb) * na + wrapi(a0 + la - 2, na);
                         const int kw = Fd.widx[n];
                         real rw = Fd.phi[kw] * rave - Fd.drho[kw];
                         rw = rw > C.rho_l ? C.rho_l : rw;
@@ -183,13 +177,13 @@ __global__ __launch_bounds__(TX* TY) void k_step_march(Coef<real> C, Fields<real
         if (it >= 4 && cc < nc && own_in) {
             const int sc = (it - 2) % NSLOT;
             const int sp = (it - 2) % NPSI;
-            const size_t n = (size_t)cc * nab + own_ab;
+            const uint32_t n = (uint32_t)cc * nab + own_ab;
             const uint8_t c = s_cls[sc][own_p];
             if (c != CLS_FLUID) {
                 if (MODE == MODE_FIELDS) {
                     if (Out.rho) Out.rho[n] = (c == CLS_WALL) ? s_rho[sc][own_p] : real(0);
                     if (Out.u)
-                        for (int d = 0; d < L::D; ++d) Out.u[d * N + n] = real(0);
+                        for (int d = 0; d < L::D; ++d) Out.u[(size_t)d * N + n] = real(0);
                 }
             } else {
                 const real rho = s_rho[sc][own_p];
@@ -228,6 +222,9 @@ __global__ __launch_bounds__(TX* TY) void k_step_march(Coef<real> C, Fields<real
                     const real fa = (C.scheme == WET_SFI) ? -C.G_w * rho * sa[d] : real(0);
                     F[d] = (d < L::D) ? Fm[d] + fa + C.body[d] : real(0);
                 }
+                real fl[Q];
+#pragma unroll
+                for (int a = 0; a < Q; ++a) fl[a] = io.ld(a, n);
                 if (MODE == MODE_FIELDS) {
                     real j[3] = {real(0), real(0), real(0)};
 #pragma unroll
@@ -235,15 +232,15 @@ __global__ __launch_bounds__(TX* TY) void k_step_march(Coef<real> C, Fields<real
                         const int e3[3] = {L::ex[a], L::ey[a], L::ez[a]};
 #pragma unroll
                         for (int d = 0; d < L::D; ++d) {
-                            if (e3[d] == 1) j[d] += f2[a];
-                            if (e3[d] == -1) j[d] -= f2[a];
+                            if (e3[d] == 1) j[d] += fl[a];
+                            if (e3[d] == -1) j[d] -= fl[a];
                         }
                     }
                     real uu = real(0);
 #pragma unroll
                     for (int d = 0; d < L::D; ++d) {
                         const real ud = (j[d] + real(0.5) * F[d]) / rho;
-                        if (Out.u) Out.u[d * N + n] = ud;
+                        if (Out.u) Out.u[(size_t)d * N + n] = ud;
                         uu += ud * ud;
                     }
                     if (Out.rho) Out.rho[n] = rho;
@@ -255,7 +252,7 @@ __global__ __launch_bounds__(TX* TY) void k_step_march(Coef<real> C, Fields<real
                     d_cnt += 1;
                 } else {
                     real fs[Q], u[3];
-                    collide<L, real>(C, f2, rho, F, Fm, psi_c, fs, u);
+                    collide<L, real>(C, fl, rho, F, Fm, psi_c, fs, u);
                     const int ga = own_a, gb = D3 ? own_b : 0;
 #pragma unroll
                     for (int a = 0; a < Q; ++a) {
@@ -269,9 +266,9 @@ __global__ __launch_bounds__(TX* TY) void k_step_march(Coef<real> C, Fields<real
                             ta = ta < 0 ? ta + na : (ta >= na ? ta - na : ta);
                             tb = tb < 0 ? tb + nb : (tb >= nb ? tb - nb : tb);
                             tc = tc < 0 ? tc + nc : (tc >= nc ? tc - nc : tc);
-                            Fd.fout[a * N + (size_t)tc * nab + (size_t)tb * na + ta] = fs[a];
+                            io.st(a, (uint32_t)tc * nab + (uint32_t)tb * na + ta, fs[a]);
                         } else {
-                            Fd.fout[L::opp[a] * N + n] = fs[a];
+                            io.st(L::opp[a], n, fs[a]);
                         }
                     }
                 }
@@ -282,50 +279,142 @@ __global__ __launch_bounds__(TX* TY) void k_step_march(Coef<real> C, Fields<real
     }
 
     if (MODE == MODE_FIELDS && Out.part) {
-        block_reduce_diag<NT>(d_sum, d_umax, d_rmin, d_rmax, d_cnt,
-                              Out.part + 5 * ((blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x +
-                                              blockIdx.x));
+        block_reduce_diag<NT>(d_sum, d_umax, d_rmin, d_rmax, d_cnt, Out.part + 5 * bid);
     }
     if (bad) Fd.flag[0] = 1;
 }
 
 // ----------------------------------------------------------------- launch
-template <typename real>
-struct Tile3D;
-template <>
-struct Tile3D<float> {
-    static constexpr int TX = 32, TY = 8, TZ = 16;
-};
-template <>
-struct Tile3D<double> {
-    static constexpr int TX = 32, TY = 8, TZ = 16;
+// Sweep-tile variants the autotuner chooses among (variant 0: default and
+// the shape of the field/diagnostic mode).
+struct Shape3D {
+    int TX, TY, TZ;
+    bool xcd;
 };
 
 template <typename real>
-int grid3d_blocks(int nx, int ny, int nz) {
-    using T = Tile3D<real>;
-    return ((nx + T::TX - 1) / T::TX) * ((ny + T::TY - 1) / T::TY) * ((nz + T::TZ - 1) / T::TZ);
+struct Variants3D;
+template <>
+struct Variants3D<float> {
+    static constexpr int count = 5;
+    static constexpr Shape3D shape[count] = {
+        {32, 8, 16, true}, {32, 8, 16, false}, {32, 8, 8, true}, {32, 8, 32, true}, {16, 16, 16, true}};
+};
+template <>
+struct Variants3D<double> {
+    static constexpr int count = 2;
+    static constexpr Shape3D shape[count] = {{32, 8, 16, true}, {32, 8, 16, false}};
+};
+
+template <typename real>
+int step3d_variants() {
+    return Variants3D<real>::count;
+}
+
+template <typename real>
+int grid3d_blocks(int nx, int ny, int nz, int variant) {
+    const Shape3D s = Variants3D<real>::shape[variant];
+    return ((nx + s.TX - 1) / s.TX) * ((ny + s.TY - 1) / s.TY) * ((nz + s.TZ - 1) / s.TZ);
+}
+
+template <typename real, int V, int MODE, bool BUF = true>
+static void launch_v3(const Coef<real>& C, const Fields<real>& F, const FieldOut<real>& O,
+                      hipStream_t s) {
+    constexpr Shape3D sh = Variants3D<real>::shape[V];
+    dim3 grid((C.nx + sh.TX - 1) / sh.TX, (C.ny + sh.TY - 1) / sh.TY, (C.nz + sh.TZ - 1) / sh.TZ);
+    hipLaunchKernelGGL((k_step_march<D3Q19, real, sh.TX, sh.TY, sh.TZ, MODE, sh.xcd, BUF>), grid,
+                       dim3(sh.TX * sh.TY), 0, s, C, F, O);
+}
+
+template <typename real, int V>
+static void launch_mode3(const Coef<real>& C, const Fields<real>& F, const FieldOut<real>& O,
+                         int mode, hipStream_t s) {
+    if (mode == MODE_STEP) launch_v3<real, V, MODE_STEP>(C, F, O, s);
+    else launch_v3<real, V, MODE_FIELDS>(C, F, O, s);
 }
 
 template <typename real>
 hipError_t launch_step3d(const Coef<real>& C, const Fields<real>& F, const FieldOut<real>& O,
-                         int mode, hipStream_t s) {
-    using T = Tile3D<real>;
-    dim3 grid((C.nx + T::TX - 1) / T::TX, (C.ny + T::TY - 1) / T::TY, (C.nz + T::TZ - 1) / T::TZ);
-    if (mode == MODE_STEP)
-        hipLaunchKernelGGL((k_step_march<D3Q19, real, T::TX, T::TY, T::TZ, MODE_STEP>), grid,
-                           dim3(T::TX * T::TY), 0, s, C, F, O);
-    else
-        hipLaunchKernelGGL((k_step_march<D3Q19, real, T::TX, T::TY, T::TZ, MODE_FIELDS>), grid,
-                           dim3(T::TX * T::TY), 0, s, C, F, O);
+                         int mode, int variant, hipStream_t s) {
+    if (mode == MODE_FIELDS) variant = 0;
+    // population arrays of 4 GiB or more cannot use 32-bit buffer offsets
+    if ((uint64_t)19 * (uint64_t)C.nx * C.ny * C.nz * sizeof(real) > 0xFFFFFFFFull) {
+        if (mode == MODE_STEP) launch_v3<real, 0, MODE_STEP, false>(C, F, O, s);
+        else launch_v3<real, 0, MODE_FIELDS, false>(C, F, O, s);
+        return hipGetLastError();
+    }
+    if (variant == 0) launch_mode3<real, 0>(C, F, O, mode, s);
+    else if (variant == 1) launch_mode3<real, 1>(C, F, O, mode, s);
+    else if constexpr (Variants3D<real>::count > 2) {
+        if (variant == 2) launch_mode3<real, 2>(C, F, O, mode, s);
+        else if (variant == 3) launch_mode3<real, 3>(C, F, O, mode, s);
+        else if (variant == 4) launch_mode3<real, 4>(C, F, O, mode, s);
+        else return hipErrorInvalidValue;
+    } else {
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
-template int grid3d_blocks<float>(int, int, int);
-template int grid3d_blocks<double>(int, int, int);
+// D2Q9 sweeping along y: a TX-wide strip (TY = 1) and chunks of TZ rows
+struct Shape2M {
+    int TX, TZ;
+};
+template <typename real>
+struct Variants2M;
+template <>
+struct Variants2M<float> {
+    static constexpr int count = 3;
+    static constexpr Shape2M shape[count] = {{256, 32}, {256, 16}, {64, 16}};
+};
+template <>
+struct Variants2M<double> {
+    static constexpr int count = 1;
+    static constexpr Shape2M shape[count] = {{128, 16}};
+};
+
+template <typename real>
+int step2d_march_variants() {
+    return Variants2M<real>::count;
+}
+
+template <typename real, int V, int MODE>
+static void launch_v2m(const Coef<real>& C, const Fields<real>& F, const FieldOut<real>& O,
+                       hipStream_t s) {
+    constexpr Shape2M sh = Variants2M<real>::shape[V];
+    dim3 grid((C.nx + sh.TX - 1) / sh.TX, 1, (C.ny + sh.TZ - 1) / sh.TZ);
+    hipLaunchKernelGGL((k_step_march<D2Q9, real, sh.TX, 1, sh.TZ, MODE, true, true>), grid,
+                       dim3(sh.TX), 0, s, C, F, O);
+}
+
+// (step mode only; the caller has checked that the populations fit a buffer)
+template <typename real>
+hipError_t launch_step2d_march(const Coef<real>& C, const Fields<real>& F, const FieldOut<real>& O,
+                               int idx, hipStream_t s) {
+    if (idx == 0) launch_v2m<real, 0, MODE_STEP>(C, F, O, s);
+    else if constexpr (Variants2M<real>::count > 1) {
+        if (idx == 1) launch_v2m<real, 1, MODE_STEP>(C, F, O, s);
+        else if (idx == 2) launch_v2m<real, 2, MODE_STEP>(C, F, O, s);
+        else return hipErrorInvalidValue;
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template int step2d_march_variants<float>();
+template int step2d_march_variants<double>();
+template hipError_t launch_step2d_march<float>(const Coef<float>&, const Fields<float>&,
+                                               const FieldOut<float>&, int, hipStream_t);
+template hipError_t launch_step2d_march<double>(const Coef<double>&, const Fields<double>&,
+                                                const FieldOut<double>&, int, hipStream_t);
+template int step3d_variants<float>();
+template int step3d_variants<double>();
+template int grid3d_blocks<float>(int, int, int, int);
+template int grid3d_blocks<double>(int, int, int, int);
 template hipError_t launch_step3d<float>(const Coef<float>&, const Fields<float>&,
-                                         const FieldOut<float>&, int, hipStream_t);
+                                         const FieldOut<float>&, int, int, hipStream_t);
 template hipError_t launch_step3d<double>(const Coef<double>&, const Fields<double>&,
-                                          const FieldOut<double>&, int, hipStream_t);
+                                          const FieldOut<double>&, int, int, hipStream_t);
 
 }  // namespace lbm

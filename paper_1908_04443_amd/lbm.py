@@ -78,6 +78,10 @@ def lib():
             "lbm_step_timed": (C.c_int, [vp, i64, dp]),
             "lbm_get_fields": (C.c_int, [vp, vp, vp, vp]),
             "lbm_get_diagnostics": (C.c_int, [vp, C.POINTER(lbm_diag)]),
+            "lbm_variant_count": (C.c_int, [C.c_int32, C.c_int32]),
+            "lbm_set_variant": (C.c_int, [vp, C.c_int32]),
+            "lbm_get_variant": (C.c_int, [vp, C.POINTER(C.c_int32)]),
+            "lbm_autotune": (C.c_int, [vp, i64, vp, C.POINTER(C.c_int32), dp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -192,6 +196,31 @@ def lbm_get_diagnostics(ctx):
                     flag=d.flag, n_fluid=d.n_fluid)
 
 
+def lbm_variant_count(lattice, precision):
+    n = lib().lbm_variant_count(int(lattice), int(precision))
+    if n < 0:
+        _check(n, "lbm_variant_count")
+    return n
+
+
+def lbm_set_variant(ctx, variant):
+    _check(lib().lbm_set_variant(ctx, int(variant)), "lbm_set_variant")
+
+
+def lbm_get_variant(ctx):
+    v = C.c_int32()
+    _check(lib().lbm_get_variant(ctx, C.byref(v)), "lbm_get_variant")
+    return v.value
+
+
+def lbm_autotune(ctx, steps, save=None, nvariants=None):
+    """Returns (best variant, per-variant ms list or None)."""
+    best = C.c_int32()
+    ms = (C.c_double * nvariants)() if nvariants else None
+    _check(lib().lbm_autotune(ctx, int(steps), _ptr(save), C.byref(best), ms), "lbm_autotune")
+    return best.value, (list(ms) if ms is not None else None)
+
+
 # ---------------------------------------------------------------- helpers
 def make_params(lattice=9, precision=4, nx=64, ny=64, nz=1, tau=1.0, eos=LBM_EOS_CS,
                 a=1.0, b=4.0, R=1.0, T=None, T_ratio=0.75, omega=0.344, G=-1.0, sigma=0.0,
@@ -291,3 +320,20 @@ class Solver:
 
     def diagnostics(self):
         return lbm_get_diagnostics(self.ctx)
+
+    def autotune(self, steps=20, report=False):
+        """Pick the fastest step-kernel variant on this problem; the state is
+        saved and restored around the trials."""
+        save = torch.empty(self.Q * self.N, dtype=self.dtype, device=self.device)
+        nv = lbm_variant_count(self.p.lattice, self.p.precision) if report else None
+        best, ms = lbm_autotune(self.ctx, steps, save, nv)
+        torch.cuda.synchronize(self.device)
+        return (best, ms) if report else best
+
+    @property
+    def variant(self):
+        return lbm_get_variant(self.ctx)
+
+    @variant.setter
+    def variant(self, v):
+        lbm_set_variant(self.ctx, v)

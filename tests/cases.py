@@ -103,7 +103,7 @@ class Setup:
         self.f0 = O.init_eq(self.op, self.solid, self.rho0)
 
 
-def run_gpu(L, setup, nsteps, precision=None, n_wall_max=None, want_f=False):
+def run_gpu(L, setup, nsteps, precision=None, n_wall_max=None, want_f=False, variant=None):
     """Run the GPU library on a Setup; returns (rho, u, [f]) as numpy."""
     import torch
     case = dict(setup.case)
@@ -121,6 +121,8 @@ def run_gpu(L, setup, nsteps, precision=None, n_wall_max=None, want_f=False):
     scalar = case.get("rho_w", 0.0) if sch == 1 else case.get("G_w", 0.0)
     s.set_wetting(sch, scalar, phi if nw else None, drho if nw else None)
     s.set_fields(setup.rho0.ravel())
+    if variant is not None:
+        s.variant = variant
     s.step(nsteps)
     out = s.get_fields(rho=True, u=True, f=want_f)
     torch.cuda.synchronize()

@@ -118,3 +118,52 @@ def test_diagnostics_match_oracle(oracle_mod, gpu_lib):
     assert abs(d["rho_max"] - rho_o[fl].max()) <= 1e-12
     umag = np.sqrt((u_o ** 2).sum(0))
     assert abs(d["max_u"] - umag[fl].max()) <= 1e-12
+
+
+def _nvariants(lattice, precision):
+    from paper_1908_04443_amd import lbm
+    return lbm.lbm_variant_count(lattice, precision)
+
+
+@pytest.mark.parametrize("precision", [8, 4])
+@pytest.mark.parametrize("variant", range(9))
+def test_every_d2q9_variant(oracle_mod, gpu_lib, precision, variant):
+    if variant >= _nvariants(9, precision):
+        pytest.skip("no such variant")
+    case = dict(nx=150, ny=75, geometry=("disk", (70, 30), 12), init=("droplet", (70, 55), 10),
+                scheme="ivd", phi=1.15, noise=1e-6, seed=7, precision=precision)
+    s = Setup(oracle_mod, case)
+    res = run_gpu(gpu_lib, s, 150, variant=variant)
+    if precision == 8:
+        _compare(oracle_mod, s, res, 150, 1e-12, 1e-12)
+    else:
+        _compare(oracle_mod, s, res, 150, 1e-4, 1e-3, rel=True)
+
+
+@pytest.mark.parametrize("precision", [8, 4])
+@pytest.mark.parametrize("variant", range(5))
+def test_every_d3q19_variant(oracle_mod, gpu_lib, precision, variant):
+    if variant >= _nvariants(19, precision):
+        pytest.skip("no such variant")
+    case = dict(lattice=19, nx=40, ny=21, nz=37, T_ratio=0.8, sigma=0.0,
+                geometry=("disk", (20, 10, 12), 6), init=("droplet", (20, 10, 23), 5),
+                scheme="ivd", phi=1.1, noise=1e-6, seed=8, precision=precision)
+    s = Setup(oracle_mod, case)
+    res = run_gpu(gpu_lib, s, 40, variant=variant)
+    if precision == 8:
+        _compare(oracle_mod, s, res, 40, 1e-12, 1e-12)
+    else:
+        _compare(oracle_mod, s, res, 40, 1e-4, 1e-3, rel=True)
+
+
+def test_autotune_restores_state(oracle_mod, gpu_lib):
+    s = Setup(oracle_mod, dict(C0, precision=4))
+    res = run_gpu(gpu_lib, s, 10)
+    sol = res["solver"]
+    before = sol.get_fields(rho=True, u=False, f=True)
+    best, ms = sol.autotune(steps=3, report=True)
+    after = sol.get_fields(rho=True, u=False, f=True)
+    assert 0 <= best < len(ms) and all(m > 0 for m in ms)
+    assert sol.variant == best
+    import torch
+    assert torch.equal(before["f"], after["f"])
