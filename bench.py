@@ -114,6 +114,60 @@ def run_c2(L, W, steps, warmup):
     return dict(N=N, n_fluid=nf, n_wall=nw, wall=wall, ms_events=ms)
 
 
+def run_c3(L, W, steps, warmup, graph_steps=50):
+    """96 D2Q9 FP32 cases of uneven size: one multi-case context replaying a
+    graph of `graph_steps` steps, against one context per case stepped in
+    turn on the same stream with plain launches."""
+    import torch
+    p = L.make_params(lattice=9, precision=4, nx=1, ny=1, T_ratio=0.75,
+                      sigma=W.SIGMA[("cs", 0.75, 9)], tau=1.0)
+    cases = W.c3_cases(p.rho_g, p.rho_l)
+    sizes = [(c["n"], c["n"]) for c in cases]
+    nwm = [int(c["solid"].sum()) for c in cases]
+    total = sum(a * b for a, b in sizes)
+
+    b = L.BatchSolver(p, sizes, nwm)
+    b.set_scheme(L.LBM_WET_IVD)
+    for i, c in enumerate(cases):
+        b.set_geometry(i, c["solid"])
+        w = b.wall_nodes(i)
+        b.set_wetting(i, torch.as_tensor(c["phi"].ravel()[w], dtype=b.dtype, device="cuda"),
+                      torch.as_tensor(c["drho"].ravel()[w], dtype=b.dtype, device="cuda"))
+        b.set_fields(i, c["rho"].ravel())
+    b.set_graph_steps(graph_steps)
+    b.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    rc, d = b.diagnostics()
+    if rc != 0:
+        raise RuntimeError("batched run left the psi domain")
+    b.close()
+
+    sols = []
+    for c in cases:
+        q = L.make_params(lattice=9, precision=4, nx=c["n"], ny=c["n"], T=p.eos_T, sigma=p.sigma,
+                          tau=1.0, rho_g=p.rho_g, rho_l=p.rho_l)
+        s1, _ = setup_solver(L, W, q, c, int(c["solid"].sum()))
+        sols.append(s1)
+    for s1 in sols:
+        s1.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s1 in sols:
+        s1.step(steps)
+    torch.cuda.synchronize()
+    t_single = time.perf_counter() - t0
+    for s1 in sols:
+        s1.close()
+    return dict(total_nodes=total, cases=len(cases), steps=steps,
+                batched_mlups=total * steps / t_batch / 1e6,
+                single_mlups=total * steps / t_single / 1e6,
+                ratio=t_single / t_batch, graph_steps=graph_steps)
+
+
 def cpu_baseline(data, lbm_params, steps):
     """The CPU oracle (FP64) on the same 2048^2 lattice and initial state,
     `steps` steps."""
@@ -140,10 +194,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--cpu-steps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--c2-steps", type=int, default=500)
+    ap.add_argument("--c3-steps", type=int, default=500)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -213,6 +268,11 @@ def main():
                 "traffic": measured_traffic("k_step_march", "c2")},
         }
         log(f"C2: {out['secondary']['d3q19_256cubed_fp32']}")
+        log(f"C3: 96 uneven D2Q9 FP32 cases, {args.c3_steps} steps, batched vs one per launch")
+        c3 = run_c3(L, W, args.c3_steps, 20)
+        out["secondary"]["batched_96_cases_fp32"] = {k: (round(v, 3) if isinstance(v, float) else v)
+                                                     for k, v in c3.items()}
+        log(f"C3: {out['secondary']['batched_96_cases_fp32']}")
 
     if not args.no_cpu_baseline:
         log(f"CPU oracle: {args.cpu_steps} steps of the 2048^2 workload")

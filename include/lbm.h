@@ -221,6 +221,43 @@ int lbm_get_variant(lbm_ctx* ctx, int32_t* variant);
 int lbm_autotune(lbm_ctx* ctx, int64_t steps, void* save_dev, int32_t* best_out,
                  double* ms_per_variant);
 
+/* ------------------------------------------------------ graph replay */
+/* Replay `steps` steps (rounded up to even) as one HIP graph: lbm_step(n)
+ * then issues n / steps graph launches plus plain launches for the rest.
+ * The graph is captured on a stream of the library's own and launched on
+ * the context stream; it is captured again after a change of wetting
+ * scheme or kernel variant.  0 (the default) turns graphs off.  Captures
+ * contain kernel launches only. */
+int lbm_set_graph_steps(lbm_ctx* ctx, int64_t steps);
+
+/* ------------------------------------------------- many lattices at once */
+/* A multi-case context advances ncases independent D2Q9 lattices of their
+ * own sizes (nx[i] x ny[i], room for n_wall_max[i] wall nodes) in one
+ * launch per step: every workgroup looks up its (case, tile) in a table.
+ * The parameter block is shared (its nx, ny, nz are ignored); geometry,
+ * wetting parameters and fields are per case.  lbm_step, lbm_step_timed,
+ * lbm_set_wetting (scheme and uniform values for all cases),
+ * lbm_set_graph_steps, lbm_set_variant, lbm_autotune and
+ * lbm_get_diagnostics (totals over the cases) accept such a context; the
+ * single-lattice geometry/fields calls return LBM_EINVAL for it.  Each
+ * case's populations must stay below 4 GiB. */
+size_t lbm_batch_workspace_bytes(const lbm_params* p, int32_t ncases, const int32_t* nx,
+                                 const int32_t* ny, const int64_t* n_wall_max);
+int lbm_create_batch(const lbm_params* p, int32_t ncases, const int32_t* nx, const int32_t* ny,
+                     const int64_t* n_wall_max, void* stream, void* workspace, size_t ws_bytes,
+                     lbm_ctx** out);
+int lbm_batch_cases(lbm_ctx* ctx, int32_t* ncases);
+/* Per-case versions of the single-lattice calls (case index i). */
+int lbm_set_geometry_case(lbm_ctx* ctx, int32_t i, const uint8_t* solid_host);
+int lbm_wall_nodes_case(lbm_ctx* ctx, int32_t i, int64_t* idx_host, int64_t* count);
+/* Improved-virtual-density parameters of one case (count entries each, or
+ * NULL for the uniform phi0 / drho0). */
+int lbm_set_wetting_case(lbm_ctx* ctx, int32_t i, const void* phi_dev, const void* drho_dev,
+                         double phi0, double drho0);
+int lbm_set_fields_case(lbm_ctx* ctx, int32_t i, const void* rho_dev, const void* u_dev);
+int lbm_get_fields_case(lbm_ctx* ctx, int32_t i, void* rho_dev, void* u_dev, void* f_dev);
+int lbm_get_diagnostics_case(lbm_ctx* ctx, int32_t i, lbm_diag* host_out);
+
 #ifdef __cplusplus
 }
 #endif

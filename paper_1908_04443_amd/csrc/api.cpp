@@ -163,19 +163,141 @@ static int launch_mode(lbm_ctx* c, int mode, real* rho, real* u, double* part) {
     return LBM_OK;
 }
 
+// ---- multi-case tile table: (case, tile origin) for every tile of the
+// chosen tile shape, case by case in row-major tile order
+template <typename real>
+static int ensure_tiles(lbm_ctx* c) {
+    if (c->tiles_variant == c->variant) return LBM_OK;
+    int TX = 0, TY = 0;
+    tile2d_shape<real>(c->variant, &TX, &TY);
+    std::vector<TileRef> t;
+    for (size_t i = 0; i < c->cases.size(); ++i) {
+        const lbm_case& k = c->cases[i];
+        for (int y = 0; y < k.ny; y += TY)
+            for (int x = 0; x < k.nx; x += TX) t.push_back(TileRef{(int32_t)i, x, y, 0});
+    }
+    if ((int64_t)t.size() > c->max_tiles) return fail(LBM_EINVAL, "tile table exceeds its space");
+    LBM_HIP(hipMemcpyAsync(c->d_tiles, t.data(), t.size() * sizeof(TileRef),
+                           hipMemcpyHostToDevice, c->stream));
+    LBM_HIP(hipStreamSynchronize(c->stream));
+    c->ntiles = (int)t.size();
+    c->tiles_variant = c->variant;
+    c->graph_dirty = true;
+    return LBM_OK;
+}
+
+// one step from buffer `src` to `src ^ 1`, launched on stream s
+template <typename real>
+static hipError_t launch_one(lbm_ctx* c, const Coef<real>& C, int src, hipStream_t s) {
+    if (c->is_batch) {
+        BatchArgs<real> B;
+        B.fin = (const real*)c->f[src];
+        B.fout = (real*)c->f[src ^ 1];
+        B.cls = c->cls;
+        B.widx = c->widx;
+        B.phi = (const real*)c->phi;
+        B.drho = (const real*)c->drho;
+        B.flag = c->flag;
+        B.cases = c->d_cases;
+        B.tiles = c->d_tiles;
+        return launch_step2d_batch<real>(C, B, c->ntiles, c->variant, s);
+    }
+    Fields<real> F = make_fields<real>(c, src);
+    FieldOut<real> O{nullptr, nullptr, nullptr};
+    return (c->p.lattice == 9) ? launch_step2d<real>(C, F, O, MODE_STEP, c->variant, s)
+                               : launch_step3d<real>(C, F, O, MODE_STEP, c->variant, s);
+}
+
+static void drop_graph(lbm_ctx* c) {
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->graph_exec = nullptr;
+    c->graph = nullptr;
+    c->graph_parity = -1;
+}
+
+// Capture graph_steps (even) steps starting from buffer c->cur on the
+// library's own capture stream; the graph is replayed on the context stream.
+template <typename real>
+static int capture_graph(lbm_ctx* c, const Coef<real>& C) {
+    drop_graph(c);
+    if (!c->cap_stream) LBM_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    LBM_HIP(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
+    int src = c->cur;
+    hipError_t e = hipSuccess;
+    for (int64_t i = 0; i < c->graph_steps && e == hipSuccess; ++i) {
+        e = launch_one<real>(c, C, src, c->cap_stream);
+        src ^= 1;
+    }
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(LBM_EDEVICE, std::string("graph capture: ") +
+                                     hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    c->graph = g;
+    LBM_HIP(hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0));
+    c->graph_parity = c->cur;
+    c->graph_dirty = false;
+    return LBM_OK;
+}
+
 template <typename real>
 static int run_steps(lbm_ctx* c, int64_t nsteps) {
     Coef<real> C = make_coef<real>(c);
-    FieldOut<real> O{nullptr, nullptr, nullptr};
-    for (int64_t i = 0; i < nsteps; ++i) {
-        Fields<real> F = make_fields<real>(c, c->cur);
-        hipError_t e = (c->p.lattice == 9)
-                           ? launch_step2d<real>(C, F, O, MODE_STEP, c->variant, c->stream)
-                           : launch_step3d<real>(C, F, O, MODE_STEP, c->variant, c->stream);
+    if (c->is_batch) {
+        int rc = ensure_tiles<real>(c);
+        if (rc != LBM_OK) return rc;
+    }
+    int64_t done = 0;
+    if (c->graph_steps > 0 && nsteps >= c->graph_steps) {
+        if (c->graph_dirty || c->graph_parity != c->cur || !c->graph_exec) {
+            int rc = capture_graph<real>(c, C);
+            if (rc != LBM_OK) return rc;
+        }
+        // an even number of steps per replay leaves the buffer parity as is
+        for (; nsteps - done >= c->graph_steps; done += c->graph_steps)
+            LBM_HIP(hipGraphLaunch(c->graph_exec, c->stream));
+    }
+    for (; done < nsteps; ++done) {
+        hipError_t e = launch_one<real>(c, C, c->cur, c->stream);
         if (e != hipSuccess)
             return fail(LBM_EDEVICE, std::string("step launch: ") + hipGetErrorString(e));
         c->cur ^= 1;
     }
+    return LBM_OK;
+}
+
+// ---- per-case views of a multi-case context (single-lattice launchers)
+template <typename real>
+static Coef<real> case_coef(const lbm_ctx* c, const lbm_case& k) {
+    Coef<real> C = make_coef<real>(c);
+    C.nx = k.nx;
+    C.ny = k.ny;
+    C.nz = 1;
+    return C;
+}
+
+template <typename real>
+static Fields<real> case_fields(const lbm_ctx* c, const lbm_case& k) {
+    Fields<real> F;
+    F.fin = (const real*)c->f[c->cur] + k.f_off;
+    F.fout = (real*)c->f[c->cur ^ 1] + k.f_off;
+    F.cls = c->cls + k.node_off;
+    F.widx = c->widx + k.node_off;
+    F.phi = (const real*)c->phi + k.wall_off;
+    F.drho = (const real*)c->drho + k.wall_off;
+    F.flag = c->flag;
+    return F;
+}
+
+template <typename real>
+static int case_fields_launch(lbm_ctx* c, const lbm_case& k, real* rho, real* u, double* part) {
+    FieldOut<real> O{rho, u, part};
+    hipError_t e = launch_step2d<real>(case_coef<real>(c, k), case_fields<real>(c, k), O,
+                                       MODE_FIELDS, 0, c->stream);
+    if (e != hipSuccess) return fail(LBM_EDEVICE, std::string("field launch: ") + hipGetErrorString(e));
     return LBM_OK;
 }
 
@@ -200,6 +322,127 @@ static int fill_wetting(lbm_ctx* c, const void* phi_dev, const void* drho_dev, d
         for (int64_t i = 0; i < nw; ++i)
             if (!(h[i] > 0)) return fail(LBM_EINVAL, "phi must be positive on every wall node");
     }
+    return LBM_OK;
+}
+
+// geometry and fields set (on every case of a multi-case context)
+static bool ready(const lbm_ctx* c) {
+    if (!c->is_batch) return c->have_geom && c->have_fields;
+    for (const lbm_case& k : c->cases)
+        if (!k.have_geom || !k.have_fields) return false;
+    return !c->cases.empty();
+}
+
+static int ctx_variants(const lbm_ctx* c) {
+    if (c->is_batch) return c->prec == 4 ? tile2d_variants<float>() : tile2d_variants<double>();
+    return variant_count(c->p.lattice, c->p.precision);
+}
+
+// bytes of one population buffer (one ping-pong side)
+static size_t state_bytes(const lbm_ctx* c) {
+    if (c->is_batch) return c->f_bytes;
+    return (size_t)c->Q * c->N * c->prec;
+}
+
+// ---- multi-case layout: packed arenas for all cases
+static uint64_t round_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
+
+static size_t layout_batch(const lbm_params& p, int ncases, const int32_t* nx, const int32_t* ny,
+                           const int64_t* nwm, lbm_ctx* c) {
+    Carver cv(c ? c->ws : nullptr, c ? c->ws_bytes : 0);
+    const size_t s = (size_t)p.precision;
+    uint64_t f_off = 0, node_off = 0, wall_off = 0;
+    int64_t max_parts = 1;
+    std::vector<lbm_case> cs(ncases);
+    for (int i = 0; i < ncases; ++i) {
+        lbm_case& k = cs[i];
+        k.nx = nx[i];
+        k.ny = ny[i];
+        k.N = (int64_t)nx[i] * ny[i];
+        k.n_wall_max = nwm[i];
+        k.f_off = f_off;
+        f_off += round_up(9 * (uint64_t)k.N, 64);
+        k.node_off = node_off;
+        node_off += round_up((uint64_t)k.N, 256);
+        k.wall_off = wall_off;
+        wall_off += round_up((uint64_t)(nwm[i] > 0 ? nwm[i] : 1), 64);
+        const int parts = p.precision == 4 ? grid2d_blocks<float>(k.nx, k.ny, 0)
+                                           : grid2d_blocks<double>(k.nx, k.ny, 0);
+        max_parts = parts > max_parts ? parts : max_parts;
+    }
+    int64_t tiles_max = 0;
+    const int nv = p.precision == 4 ? tile2d_variants<float>() : tile2d_variants<double>();
+    for (int v = 0; v < nv; ++v) {
+        int TX, TY;
+        if (p.precision == 4) tile2d_shape<float>(v, &TX, &TY);
+        else tile2d_shape<double>(v, &TX, &TY);
+        int64_t t = 0;
+        for (int i = 0; i < ncases; ++i)
+            t += (int64_t)((nx[i] + TX - 1) / TX) * ((ny[i] + TY - 1) / TY);
+        tiles_max = t > tiles_max ? t : tiles_max;
+    }
+    void* f0 = cv.take<char>(f_off * s);
+    void* f1 = cv.take<char>(f_off * s);
+    uint8_t* cls = cv.take<uint8_t>(node_off);
+    int32_t* widx = cv.take<int32_t>(node_off);
+    void* phi = cv.take<char>(wall_off * s);
+    void* drho = cv.take<char>(wall_off * s);
+    CaseDesc* dc = cv.take<CaseDesc>(ncases);
+    TileRef* dt = cv.take<TileRef>(tiles_max);
+    int32_t* flag = cv.take<int32_t>(4);
+    double* part = cv.take<double>(5 * (size_t)max_parts);
+    double* dout = cv.take<double>(8);
+    if (c) {
+        c->f[0] = f0;
+        c->f[1] = f1;
+        c->cls = cls;
+        c->widx = widx;
+        c->phi = phi;
+        c->drho = drho;
+        c->d_cases = dc;
+        c->d_tiles = dt;
+        c->max_tiles = tiles_max;
+        c->flag = flag;
+        c->part = part;
+        c->diag_out = dout;
+        c->nparts = (int)max_parts;
+        c->f_bytes = f_off * s;
+        c->n_wall_max = (int64_t)wall_off;
+        int64_t N = 0;
+        for (auto& k : cs) N += k.N;
+        c->N = N;
+        c->cases = std::move(cs);
+    }
+    return (cv.off + 255) & ~size_t(255);
+}
+
+static int check_batch_args(const lbm_params* p, int32_t ncases, const int32_t* nx,
+                            const int32_t* ny, const int64_t* nwm) {
+    if (!p || !nx || !ny || !nwm) return fail(LBM_EINVAL, "NULL argument");
+    if (p->lattice != 9) return fail(LBM_EINVAL, "multi-case contexts are D2Q9");
+    if (ncases < 1) return fail(LBM_EINVAL, "ncases must be >= 1");
+    lbm_params q = *p;
+    q.nx = q.ny = q.nz = 1;
+    int rc = validate(&q);
+    if (rc != LBM_OK) return rc;
+    for (int i = 0; i < ncases; ++i) {
+        if (nx[i] < 1 || ny[i] < 1 || nwm[i] < 0) return fail(LBM_EINVAL, "bad case size");
+        if ((uint64_t)9 * nx[i] * ny[i] * p->precision > 0xFFFFFFFFull)
+            return fail(LBM_EINVAL, "a case's populations must stay below 4 GiB");
+    }
+    return LBM_OK;
+}
+
+template <typename real>
+static int upload_cases(lbm_ctx* c) {
+    std::vector<CaseDesc> d(c->cases.size());
+    for (size_t i = 0; i < d.size(); ++i) {
+        const lbm_case& k = c->cases[i];
+        d[i] = CaseDesc{k.nx, k.ny, k.f_off, k.node_off, k.wall_off};
+    }
+    LBM_HIP(hipMemcpyAsync(c->d_cases, d.data(), d.size() * sizeof(CaseDesc),
+                           hipMemcpyHostToDevice, c->stream));
+    LBM_HIP(hipStreamSynchronize(c->stream));
     return LBM_OK;
 }
 
@@ -290,6 +533,8 @@ int lbm_create(const lbm_params* p, void* stream, void* workspace, size_t ws_byt
 
 int lbm_destroy(lbm_ctx* c) {
     if (!c) return LBM_OK;
+    drop_graph(c);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     delete c;
@@ -298,6 +543,7 @@ int lbm_destroy(lbm_ctx* c) {
 
 int lbm_set_geometry(lbm_ctx* c, const uint8_t* solid_host) {
     if (!c || !solid_host) return fail(LBM_EINVAL, "NULL argument");
+    if (c->is_batch) return fail(LBM_EINVAL, "multi-case context: use the _case call");
     Geometry g;
     build_geometry(c->p, solid_host, g);
     if ((int64_t)g.walls.size() > c->n_wall_max)
@@ -328,6 +574,7 @@ int lbm_set_geometry(lbm_ctx* c, const uint8_t* solid_host) {
 
 int lbm_wall_nodes(lbm_ctx* c, int64_t* idx_host, int64_t* count) {
     if (!c || !count) return fail(LBM_EINVAL, "NULL argument");
+    if (c->is_batch) return fail(LBM_EINVAL, "multi-case context: use the _case call");
     if (!c->have_geom) return fail(LBM_ESTATE, "no geometry set");
     *count = (int64_t)c->geom.walls.size();
     if (idx_host)
@@ -338,13 +585,29 @@ int lbm_wall_nodes(lbm_ctx* c, int64_t* idx_host, int64_t* count) {
 int lbm_set_wetting(lbm_ctx* c, int32_t scheme, double scalar, const void* phi_dev,
                     const void* drho_dev, double phi0, double drho0) {
     if (!c) return fail(LBM_EINVAL, "NULL context");
-    if (!c->have_geom) return fail(LBM_ESTATE, "set the geometry before the wetting scheme");
+    if (!c->is_batch && !c->have_geom)
+        return fail(LBM_ESTATE, "set the geometry before the wetting scheme");
     if (scheme == LBM_WET_IVD) {
         if (!phi_dev && !(phi0 > 0)) return fail(LBM_EINVAL, "phi must be positive");
         if (!std::isfinite(drho0)) return fail(LBM_EINVAL, "drho must be finite");
-        int rc = (c->prec == 4) ? fill_wetting<float>(c, phi_dev, drho_dev, phi0, drho0)
-                                : fill_wetting<double>(c, phi_dev, drho_dev, phi0, drho0);
-        if (rc != LBM_OK) return rc;
+        if (c->is_batch) {
+            // every case gets the uniform values; per-case arrays go through
+            // lbm_set_wetting_case
+            if (phi_dev || drho_dev)
+                return fail(LBM_EINVAL, "multi-case context: per-node arrays need lbm_set_wetting_case");
+            const int64_t nw = c->n_wall_max;
+            if (c->prec == 4) {
+                LBM_HIP(launch_fill<float>((float*)c->phi, (float)phi0, nw, c->stream));
+                LBM_HIP(launch_fill<float>((float*)c->drho, (float)drho0, nw, c->stream));
+            } else {
+                LBM_HIP(launch_fill<double>((double*)c->phi, phi0, nw, c->stream));
+                LBM_HIP(launch_fill<double>((double*)c->drho, drho0, nw, c->stream));
+            }
+        } else {
+            int rc = (c->prec == 4) ? fill_wetting<float>(c, phi_dev, drho_dev, phi0, drho0)
+                                    : fill_wetting<double>(c, phi_dev, drho_dev, phi0, drho0);
+            if (rc != LBM_OK) return rc;
+        }
     } else if (scheme == LBM_WET_VD) {
         if (!(scalar > 0) || !(psi_argument(c->p, scalar) >= 0))
             return fail(LBM_EINVAL, "virtual density outside the range where psi is real");
@@ -355,11 +618,13 @@ int lbm_set_wetting(lbm_ctx* c, int32_t scheme, double scalar, const void* phi_d
     }
     c->scheme = scheme;
     c->scalar = scalar;
+    c->graph_dirty = true;  // the scheme is part of the captured launch arguments
     return LBM_OK;
 }
 
 int lbm_set_fields(lbm_ctx* c, const void* rho_dev, const void* u_dev) {
     if (!c || !rho_dev) return fail(LBM_EINVAL, "NULL argument");
+    if (c->is_batch) return fail(LBM_EINVAL, "multi-case context: use the _case call");
     if (!c->have_geom) return fail(LBM_ESTATE, "set the geometry before the fields");
     const int64_t QN = (int64_t)c->Q * c->N;
     if (c->prec == 4) {
@@ -380,6 +645,7 @@ int lbm_set_fields(lbm_ctx* c, const void* rho_dev, const void* u_dev) {
 
 int lbm_set_state(lbm_ctx* c, const void* f_dev) {
     if (!c || !f_dev) return fail(LBM_EINVAL, "NULL argument");
+    if (c->is_batch) return fail(LBM_EINVAL, "multi-case context: use the _case call");
     if (!c->have_geom) return fail(LBM_ESTATE, "set the geometry before the state");
     const int64_t QN = (int64_t)c->Q * c->N;
     LBM_HIP(hipMemcpyAsync(c->f[c->cur], f_dev, (size_t)QN * c->prec, hipMemcpyDeviceToDevice,
@@ -400,14 +666,14 @@ int lbm_set_state(lbm_ctx* c, const void* f_dev) {
 int lbm_step(lbm_ctx* c, int64_t nsteps) {
     if (!c) return fail(LBM_EINVAL, "NULL context");
     if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
-    if (!c->have_geom || !c->have_fields) return fail(LBM_ESTATE, "geometry and fields must be set");
+    if (!ready(c)) return fail(LBM_ESTATE, "geometry and fields must be set");
     if (c->domain_error) return fail(LBM_EDOMAIN, "a previous step left the psi domain");
     return c->prec == 4 ? run_steps<float>(c, nsteps) : run_steps<double>(c, nsteps);
 }
 
 int lbm_step_timed(lbm_ctx* c, int64_t nsteps, double* ms_total) {
     if (!c || !ms_total) return fail(LBM_EINVAL, "NULL argument");
-    if (!c->have_geom || !c->have_fields) return fail(LBM_ESTATE, "geometry and fields must be set");
+    if (!ready(c)) return fail(LBM_ESTATE, "geometry and fields must be set");
     if (c->domain_error) return fail(LBM_EDOMAIN, "a previous step left the psi domain");
     LBM_HIP(hipEventRecord(c->ev0, c->stream));
     int rc = c->prec == 4 ? run_steps<float>(c, nsteps) : run_steps<double>(c, nsteps);
@@ -422,6 +688,7 @@ int lbm_step_timed(lbm_ctx* c, int64_t nsteps, double* ms_total) {
 
 int lbm_get_fields(lbm_ctx* c, void* rho_dev, void* u_dev, void* f_dev) {
     if (!c) return fail(LBM_EINVAL, "NULL context");
+    if (c->is_batch) return fail(LBM_EINVAL, "multi-case context: use the _case call");
     if (!c->have_geom || !c->have_fields) return fail(LBM_ESTATE, "geometry and fields must be set");
     if (rho_dev || u_dev) {
         int rc = c->prec == 4 ? launch_mode<float>(c, MODE_FIELDS, (float*)rho_dev, (float*)u_dev, nullptr)
@@ -437,7 +704,26 @@ int lbm_get_fields(lbm_ctx* c, void* rho_dev, void* u_dev, void* f_dev) {
 
 int lbm_get_diagnostics(lbm_ctx* c, lbm_diag* out) {
     if (!c || !out) return fail(LBM_EINVAL, "NULL argument");
-    if (!c->have_geom || !c->have_fields) return fail(LBM_ESTATE, "geometry and fields must be set");
+    if (!ready(c)) return fail(LBM_ESTATE, "geometry and fields must be set");
+    if (c->is_batch) {
+        // combine the per-case reductions (fixed case order)
+        lbm_diag acc{0.0, 0.0, 1e300, -1e300, 0, 0};
+        int worst = LBM_OK;
+        for (int32_t i = 0; i < (int32_t)c->cases.size(); ++i) {
+            lbm_diag d;
+            int rc = lbm_get_diagnostics_case(c, i, &d);
+            if (rc != LBM_OK && rc != LBM_EDOMAIN) return rc;
+            if (rc == LBM_EDOMAIN) worst = rc;
+            acc.mass += d.mass;
+            acc.max_u = d.max_u > acc.max_u ? d.max_u : acc.max_u;
+            acc.rho_min = d.rho_min < acc.rho_min ? d.rho_min : acc.rho_min;
+            acc.rho_max = d.rho_max > acc.rho_max ? d.rho_max : acc.rho_max;
+            acc.flag |= d.flag;
+            acc.n_fluid += d.n_fluid;
+        }
+        *out = acc;
+        return worst == LBM_OK ? LBM_OK : fail(worst, "psi argument became negative or NaN");
+    }
     int rc = c->prec == 4 ? launch_mode<float>(c, MODE_FIELDS, nullptr, nullptr, c->part)
                           : launch_mode<double>(c, MODE_FIELDS, nullptr, nullptr, c->part);
     if (rc != LBM_OK) return rc;
@@ -468,9 +754,9 @@ int lbm_variant_count(int32_t lattice, int32_t precision) {
 
 int lbm_set_variant(lbm_ctx* c, int32_t variant) {
     if (!c) return fail(LBM_EINVAL, "NULL context");
-    if (variant < 0 || variant >= variant_count(c->p.lattice, c->p.precision))
-        return fail(LBM_EINVAL, "variant out of range");
+    if (variant < 0 || variant >= ctx_variants(c)) return fail(LBM_EINVAL, "variant out of range");
     c->variant = variant;
+    c->graph_dirty = true;
     return LBM_OK;
 }
 
@@ -484,14 +770,15 @@ int lbm_autotune(lbm_ctx* c, int64_t steps, void* save_dev, int32_t* best_out,
                  double* ms_per_variant) {
     if (!c) return fail(LBM_EINVAL, "NULL context");
     if (steps < 1) return fail(LBM_EINVAL, "steps must be >= 1");
-    if (!c->have_geom || !c->have_fields) return fail(LBM_ESTATE, "geometry and fields must be set");
+    if (!ready(c)) return fail(LBM_ESTATE, "geometry and fields must be set");
     if (c->domain_error) return fail(LBM_EDOMAIN, "a previous step left the psi domain");
-    const int nv = variant_count(c->p.lattice, c->p.precision);
-    const size_t fbytes = (size_t)c->Q * c->N * c->prec;
+    const int nv = ctx_variants(c);
+    const size_t fbytes = state_bytes(c);
     const char* cache = std::getenv("LBM_AUTOTUNE_CACHE");
     char key[160];
-    std::snprintf(key, sizeof key, "lattice=%d precision=%d nx=%d ny=%d nz=%d", c->p.lattice,
-                  c->p.precision, c->p.nx, c->p.ny, c->p.nz);
+    std::snprintf(key, sizeof key, "lattice=%d precision=%d nx=%d ny=%d nz=%d cases=%d",
+                  c->p.lattice, c->p.precision, c->p.nx, c->p.ny, c->p.nz,
+                  c->is_batch ? (int)c->cases.size() : 1);
     if (cache && !ms_per_variant) {
         if (FILE* fp = std::fopen(cache, "r")) {
             char line[256];
@@ -505,6 +792,7 @@ int lbm_autotune(lbm_ctx* c, int64_t steps, void* save_dev, int32_t* best_out,
             std::fclose(fp);
             if (found >= 0 && found < nv) {
                 c->variant = found;
+                c->graph_dirty = true;
                 if (best_out) *best_out = found;
                 return LBM_OK;
             }
@@ -544,6 +832,7 @@ int lbm_autotune(lbm_ctx* c, int64_t steps, void* save_dev, int32_t* best_out,
         LBM_HIP(hipStreamSynchronize(c->stream));
     }
     c->variant = best;
+    c->graph_dirty = true;
     if (best_out) *best_out = best;
     if (cache) {
         if (FILE* fp = std::fopen(cache, "a")) {
@@ -551,6 +840,202 @@ int lbm_autotune(lbm_ctx* c, int64_t steps, void* save_dev, int32_t* best_out,
             std::fclose(fp);
         }
     }
+    return LBM_OK;
+}
+
+size_t lbm_batch_workspace_bytes(const lbm_params* p, int32_t ncases, const int32_t* nx,
+                                 const int32_t* ny, const int64_t* n_wall_max) {
+    if (check_batch_args(p, ncases, nx, ny, n_wall_max) != LBM_OK) return 0;
+    return layout_batch(*p, ncases, nx, ny, n_wall_max, nullptr);
+}
+
+int lbm_create_batch(const lbm_params* p, int32_t ncases, const int32_t* nx, const int32_t* ny,
+                     const int64_t* n_wall_max, void* stream, void* workspace, size_t ws_bytes,
+                     lbm_ctx** out) {
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = check_batch_args(p, ncases, nx, ny, n_wall_max);
+    if (rc != LBM_OK) return rc;
+    const size_t need = layout_batch(*p, ncases, nx, ny, n_wall_max, nullptr);
+    if (!workspace || ws_bytes < need)
+        return fail(LBM_ENOMEM, "workspace needs " + std::to_string(need) + " bytes");
+    if (((uintptr_t)workspace & 255) != 0) return fail(LBM_EINVAL, "workspace must be 256-byte aligned");
+    lbm_ctx* c = new (std::nothrow) lbm_ctx();
+    if (!c) return fail(LBM_EINVAL, "host allocation failed");
+    c->p = *p;
+    c->p.nx = c->p.ny = c->p.nz = 0;
+    c->Q = 9;
+    c->D = 2;
+    c->prec = p->precision;
+    c->stream = (hipStream_t)stream;
+    c->ws = workspace;
+    c->ws_bytes = ws_bytes;
+    c->is_batch = true;
+    layout_batch(*p, ncases, nx, ny, n_wall_max, c);
+    if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+        delete c;
+        return fail(LBM_EDEVICE, "hipEventCreate failed");
+    }
+    rc = c->prec == 4 ? upload_cases<float>(c) : upload_cases<double>(c);
+    if (rc != LBM_OK) {
+        lbm_destroy(c);
+        return rc;
+    }
+    *out = c;
+    return LBM_OK;
+}
+
+int lbm_batch_cases(lbm_ctx* c, int32_t* ncases) {
+    if (!c || !ncases) return fail(LBM_EINVAL, "NULL argument");
+    *ncases = c->is_batch ? (int32_t)c->cases.size() : 1;
+    return LBM_OK;
+}
+
+static int case_of(lbm_ctx* c, int32_t i, lbm_case** k) {
+    if (!c) return fail(LBM_EINVAL, "NULL context");
+    if (!c->is_batch) return fail(LBM_EINVAL, "not a multi-case context");
+    if (i < 0 || i >= (int32_t)c->cases.size()) return fail(LBM_EINVAL, "case index out of range");
+    *k = &c->cases[i];
+    return LBM_OK;
+}
+
+int lbm_set_geometry_case(lbm_ctx* c, int32_t i, const uint8_t* solid_host) {
+    lbm_case* k;
+    int rc = case_of(c, i, &k);
+    if (rc != LBM_OK) return rc;
+    if (!solid_host) return fail(LBM_EINVAL, "NULL geometry");
+    lbm_params q = c->p;
+    q.nx = k->nx;
+    q.ny = k->ny;
+    q.nz = 1;
+    Geometry g;
+    build_geometry(q, solid_host, g);
+    if ((int64_t)g.walls.size() > k->n_wall_max)
+        return fail(LBM_EINVAL, "case geometry has more wall nodes than its n_wall_max");
+    if (g.n_fluid == 0) return fail(LBM_EINVAL, "case geometry has no fluid node");
+    LBM_HIP(hipMemcpyAsync(c->cls + k->node_off, g.cls.data(), (size_t)k->N,
+                           hipMemcpyHostToDevice, c->stream));
+    LBM_HIP(hipMemcpyAsync(c->widx + k->node_off, g.widx.data(), (size_t)k->N * 4,
+                           hipMemcpyHostToDevice, c->stream));
+    LBM_HIP(hipStreamSynchronize(c->stream));
+    const int64_t nw = (int64_t)g.walls.size();
+    if (c->prec == 4) {
+        LBM_HIP(launch_fill<float>((float*)c->phi + k->wall_off, 1.f, nw, c->stream));
+        LBM_HIP(launch_fill<float>((float*)c->drho + k->wall_off, 0.f, nw, c->stream));
+    } else {
+        LBM_HIP(launch_fill<double>((double*)c->phi + k->wall_off, 1.0, nw, c->stream));
+        LBM_HIP(launch_fill<double>((double*)c->drho + k->wall_off, 0.0, nw, c->stream));
+    }
+    k->geom = std::move(g);
+    k->have_geom = true;
+    k->have_fields = false;
+    return LBM_OK;
+}
+
+int lbm_wall_nodes_case(lbm_ctx* c, int32_t i, int64_t* idx_host, int64_t* count) {
+    lbm_case* k;
+    int rc = case_of(c, i, &k);
+    if (rc != LBM_OK) return rc;
+    if (!count) return fail(LBM_EINVAL, "NULL count");
+    if (!k->have_geom) return fail(LBM_ESTATE, "no geometry set for this case");
+    *count = (int64_t)k->geom.walls.size();
+    if (idx_host)
+        for (size_t j = 0; j < k->geom.walls.size(); ++j) idx_host[j] = k->geom.walls[j];
+    return LBM_OK;
+}
+
+int lbm_set_wetting_case(lbm_ctx* c, int32_t i, const void* phi_dev, const void* drho_dev,
+                         double phi0, double drho0) {
+    lbm_case* k;
+    int rc = case_of(c, i, &k);
+    if (rc != LBM_OK) return rc;
+    if (!k->have_geom) return fail(LBM_ESTATE, "no geometry set for this case");
+    if (!phi_dev && !(phi0 > 0)) return fail(LBM_EINVAL, "phi must be positive");
+    const int64_t nw = (int64_t)k->geom.walls.size();
+    if (nw == 0) return LBM_OK;
+    const size_t bytes = (size_t)nw * c->prec;
+    char* ph = (char*)c->phi + k->wall_off * c->prec;
+    char* dr = (char*)c->drho + k->wall_off * c->prec;
+    if (phi_dev) LBM_HIP(hipMemcpyAsync(ph, phi_dev, bytes, hipMemcpyDeviceToDevice, c->stream));
+    else if (c->prec == 4) LBM_HIP(launch_fill<float>((float*)ph, (float)phi0, nw, c->stream));
+    else LBM_HIP(launch_fill<double>((double*)ph, phi0, nw, c->stream));
+    if (drho_dev) LBM_HIP(hipMemcpyAsync(dr, drho_dev, bytes, hipMemcpyDeviceToDevice, c->stream));
+    else if (c->prec == 4) LBM_HIP(launch_fill<float>((float*)dr, (float)drho0, nw, c->stream));
+    else LBM_HIP(launch_fill<double>((double*)dr, drho0, nw, c->stream));
+    return LBM_OK;
+}
+
+int lbm_set_fields_case(lbm_ctx* c, int32_t i, const void* rho_dev, const void* u_dev) {
+    lbm_case* k;
+    int rc = case_of(c, i, &k);
+    if (rc != LBM_OK) return rc;
+    if (!rho_dev) return fail(LBM_EINVAL, "NULL rho");
+    if (!k->have_geom) return fail(LBM_ESTATE, "set the case geometry before its fields");
+    const int64_t QN = 9 * k->N;
+    if (c->prec == 4) {
+        LBM_HIP(launch_init_eq<float>(9, c->cls + k->node_off, (const float*)rho_dev,
+                                      (const float*)u_dev, (float*)c->f[c->cur] + k->f_off, k->N,
+                                      c->stream));
+        LBM_HIP(launch_fill<float>((float*)c->f[c->cur ^ 1] + k->f_off, 0.f, QN, c->stream));
+    } else {
+        LBM_HIP(launch_init_eq<double>(9, c->cls + k->node_off, (const double*)rho_dev,
+                                       (const double*)u_dev, (double*)c->f[c->cur] + k->f_off,
+                                       k->N, c->stream));
+        LBM_HIP(launch_fill<double>((double*)c->f[c->cur ^ 1] + k->f_off, 0.0, QN, c->stream));
+    }
+    LBM_HIP(launch_fill_i32(c->flag, 0, 4, c->stream));
+    k->have_fields = true;
+    c->domain_error = false;
+    return LBM_OK;
+}
+
+int lbm_get_fields_case(lbm_ctx* c, int32_t i, void* rho_dev, void* u_dev, void* f_dev) {
+    lbm_case* k;
+    int rc = case_of(c, i, &k);
+    if (rc != LBM_OK) return rc;
+    if (!k->have_geom || !k->have_fields) return fail(LBM_ESTATE, "case geometry and fields must be set");
+    if (rho_dev || u_dev) {
+        rc = c->prec == 4 ? case_fields_launch<float>(c, *k, (float*)rho_dev, (float*)u_dev, nullptr)
+                          : case_fields_launch<double>(c, *k, (double*)rho_dev, (double*)u_dev, nullptr);
+        if (rc != LBM_OK) return rc;
+    }
+    if (f_dev)
+        LBM_HIP(hipMemcpyAsync(f_dev, (char*)c->f[c->cur] + k->f_off * c->prec,
+                               (size_t)9 * k->N * c->prec, hipMemcpyDeviceToDevice, c->stream));
+    return LBM_OK;
+}
+
+int lbm_get_diagnostics_case(lbm_ctx* c, int32_t i, lbm_diag* out) {
+    lbm_case* k;
+    int rc = case_of(c, i, &k);
+    if (rc != LBM_OK) return rc;
+    if (!out) return fail(LBM_EINVAL, "NULL output");
+    if (!k->have_geom || !k->have_fields) return fail(LBM_ESTATE, "case geometry and fields must be set");
+    rc = c->prec == 4 ? case_fields_launch<float>(c, *k, nullptr, nullptr, c->part)
+                      : case_fields_launch<double>(c, *k, nullptr, nullptr, c->part);
+    if (rc != LBM_OK) return rc;
+    const int parts = c->prec == 4 ? grid2d_blocks<float>(k->nx, k->ny, 0)
+                                   : grid2d_blocks<double>(k->nx, k->ny, 0);
+    LBM_HIP(launch_diag_final(c->part, parts, c->diag_out, c->stream));
+    double h[5];
+    int32_t flag[4];
+    LBM_HIP(hipMemcpyAsync(h, c->diag_out, sizeof h, hipMemcpyDeviceToHost, c->stream));
+    LBM_HIP(hipMemcpyAsync(flag, c->flag, sizeof flag, hipMemcpyDeviceToHost, c->stream));
+    LBM_HIP(hipStreamSynchronize(c->stream));
+    *out = lbm_diag{h[0], h[1], h[2], h[3], flag[0], (int32_t)h[4]};
+    if (flag[0]) {
+        c->domain_error = true;
+        return fail(LBM_EDOMAIN, "psi argument became negative or NaN");
+    }
+    return LBM_OK;
+}
+
+int lbm_set_graph_steps(lbm_ctx* c, int64_t steps) {
+    if (!c) return fail(LBM_EINVAL, "NULL context");
+    if (steps < 0) return fail(LBM_EINVAL, "steps must be >= 0");
+    drop_graph(c);
+    c->graph_steps = (steps + 1) / 2 * 2;  // even: a replay keeps the buffer parity
+    c->graph_dirty = true;
     return LBM_OK;
 }
 

@@ -9,6 +9,7 @@
 
 #include "../../include/lbm.h"
 #include "lbm_kernels.hpp"
+#include "lbm_kernels.hpp"
 
 namespace lbm {
 
@@ -61,6 +62,15 @@ struct Carver {
 
 }  // namespace lbm
 
+// one lattice of a multi-case context
+struct lbm_case {
+    int nx = 0, ny = 0;
+    int64_t N = 0, n_wall_max = 0;
+    uint64_t f_off = 0, node_off = 0, wall_off = 0;
+    lbm::Geometry geom;
+    bool have_geom = false, have_fields = false;
+};
+
 // the context (opaque in the C ABI)
 struct lbm_ctx {
     lbm_params p;
@@ -90,4 +100,20 @@ struct lbm_ctx {
     int variant = 0;  // step-kernel tile variant (autotuner choice)
     double scalar = 0.0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // multi-case contexts
+    bool is_batch = false;
+    size_t f_bytes = 0;  // bytes of one population arena
+    std::vector<lbm_case> cases;
+    lbm::CaseDesc* d_cases = nullptr;
+    lbm::TileRef* d_tiles = nullptr;
+    int64_t max_tiles = 0;
+    int ntiles = 0;
+    int tiles_variant = -1;  // variant the uploaded tile table was built for
+    // graph replay of `graph_steps` steps (0: plain launches)
+    int64_t graph_steps = 0;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    int graph_parity = -1;
+    bool graph_dirty = true;
 };

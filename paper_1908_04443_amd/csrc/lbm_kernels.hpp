@@ -20,6 +20,32 @@ struct FieldOut {
     double* part;
 };
 
+// Multi-case (batched) D2Q9 stepping: per-case descriptors and the
+// workgroup -> (case, tile) table.  Offsets are element offsets into the
+// packed arenas (populations: per ping-pong arena; node classes and wall
+// indices: per-node arena; wetting parameters: per-wall arena).
+struct CaseDesc {
+    int32_t nx, ny;
+    uint64_t f_off;
+    uint64_t node_off;
+    uint64_t wall_off;
+};
+struct TileRef {
+    int32_t c, x0, y0, pad;
+};
+template <typename real>
+struct BatchArgs {
+    const real* fin;
+    real* fout;
+    const uint8_t* cls;
+    const int32_t* widx;
+    const real* phi;
+    const real* drho;
+    int32_t* flag;
+    const CaseDesc* cases;
+    const TileRef* tiles;
+};
+
 // wave64 butterfly reduction followed by a fixed-order pass over the waves of
 // the workgroup: the result does not depend on scheduling.
 template <int NT, typename real>
@@ -78,6 +104,13 @@ int grid2d_blocks(int nx, int ny, int variant);
 template <typename real>
 hipError_t launch_step2d(const Coef<real>& C, const Fields<real>& F, const FieldOut<real>& O,
                          int mode, int variant, hipStream_t s);
+template <typename real>
+int tile2d_variants();
+template <typename real>
+void tile2d_shape(int variant, int* TX, int* TY);
+template <typename real>
+hipError_t launch_step2d_batch(const Coef<real>& C, const BatchArgs<real>& B, int ntiles,
+                               int variant, hipStream_t s);
 template <typename real>
 int step2d_march_variants();
 template <typename real>

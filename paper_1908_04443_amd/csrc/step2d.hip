@@ -24,9 +24,13 @@
 
 namespace lbm {
 
-template <typename real, int TX, int TY, int NT, int MODE, bool XCD, bool BUF>
-__global__ __launch_bounds__(NT) void k_step_d2q9(Coef<real> C, Fields<real> Fd,
-                                                  FieldOut<real> Out) {
+// The work of one TX x TY tile at (x0, y0) of an nx x ny lattice; shared by
+// the single-lattice kernel and the multi-case kernel.  part: index of this
+// tile's diagnostic partial.
+template <typename real, int TX, int TY, int NT, int MODE, bool BUF>
+__device__ __forceinline__ void d2q9_tile(const Coef<real>& C, const Fields<real>& Fd,
+                                          const FieldOut<real>& Out, const int nx, const int ny,
+                                          const int x0, const int y0, const int part) {
     using L = D2Q9;
     constexpr int LX = TX + 4, LY = TY + 4;  // tile + 2-node halo
     constexpr int ROWS = NT / TX;
@@ -40,13 +44,8 @@ __global__ __launch_bounds__(NT) void k_step_d2q9(Coef<real> C, Fields<real> Fd,
     __shared__ uint32_t s_col[LX];  // wrapped x of each halo column
     __shared__ uint32_t s_row[LY];  // wrapped y * nx of each halo row
 
-    const int nx = C.nx, ny = C.ny;
     const uint32_t N = (uint32_t)nx * (uint32_t)ny;
     const PopIO<real, BUF> io(Fd.fin, Fd.fout, N, 9);
-    const int gxb = gridDim.x, nblk = gridDim.x * gridDim.y;
-    int bid = blockIdx.x + gxb * blockIdx.y;
-    if (XCD) bid = remap_xcd(bid, nblk);
-    const int x0 = (bid % gxb) * TX, y0 = (bid / gxb) * TY;
     const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
     bool bad = false;
 
@@ -237,9 +236,39 @@ __global__ __launch_bounds__(NT) void k_step_d2q9(Coef<real> C, Fields<real> Fd,
     }
 
     if (MODE == MODE_FIELDS && Out.part) {
-        block_reduce_diag<NT>(d_sum, d_umax, d_rmin, d_rmax, d_cnt, Out.part + 5 * bid);
+        block_reduce_diag<NT>(d_sum, d_umax, d_rmin, d_rmax, d_cnt, Out.part + 5 * part);
     }
     if (bad) Fd.flag[0] = 1;
+}
+
+template <typename real, int TX, int TY, int NT, int MODE, bool XCD, bool BUF>
+__global__ __launch_bounds__(NT) void k_step_d2q9(Coef<real> C, Fields<real> Fd,
+                                                  FieldOut<real> Out) {
+    const int gxb = gridDim.x, nblk = gridDim.x * gridDim.y;
+    int bid = blockIdx.x + gxb * blockIdx.y;
+    if (XCD) bid = remap_xcd(bid, nblk);
+    d2q9_tile<real, TX, TY, NT, MODE, BUF>(C, Fd, Out, C.nx, C.ny, (bid % gxb) * TX,
+                                           (bid / gxb) * TY, bid);
+}
+
+// Many independent lattices in one launch: workgroup -> (case, tile) through
+// a table; each case has its own size, node classes, wall list and wetting
+// parameters inside packed arenas.  The physical parameters are shared.
+template <typename real, int TX, int TY, int NT, bool BUF>
+__global__ __launch_bounds__(NT) void k_step_d2q9_batch(Coef<real> C, BatchArgs<real> B) {
+    const int bid = remap_xcd(blockIdx.x, gridDim.x);
+    const TileRef t = B.tiles[bid];
+    const CaseDesc cd = B.cases[t.c];
+    Fields<real> Fd;
+    Fd.fin = B.fin + cd.f_off;
+    Fd.fout = B.fout + cd.f_off;
+    Fd.cls = B.cls + cd.node_off;
+    Fd.widx = B.widx + cd.node_off;
+    Fd.phi = B.phi + cd.wall_off;
+    Fd.drho = B.drho + cd.wall_off;
+    Fd.flag = B.flag;
+    FieldOut<real> none{nullptr, nullptr, nullptr};
+    d2q9_tile<real, TX, TY, NT, MODE_STEP, BUF>(C, Fd, none, cd.nx, cd.ny, t.x0, t.y0, bid);
 }
 
 // ----------------------------------------------------------------- launch
@@ -328,6 +357,54 @@ hipError_t launch_step2d(const Coef<real>& C, const Fields<real>& F, const Field
     return hipGetLastError();
 }
 
+template <typename real>
+int tile2d_variants() {
+    return Variants2D<real>::count;
+}
+
+template <typename real>
+void tile2d_shape(int variant, int* TX, int* TY) {
+    const Shape2D sh = Variants2D<real>::shape[variant];
+    *TX = sh.TX;
+    *TY = sh.TY;
+}
+
+template <typename real, int V>
+static void launch_b(const Coef<real>& C, const BatchArgs<real>& B, int ntiles, hipStream_t s) {
+    constexpr Shape2D sh = Variants2D<real>::shape[V];
+    hipLaunchKernelGGL((k_step_d2q9_batch<real, sh.TX, sh.TY, sh.NT, true>), dim3(ntiles),
+                       dim3(sh.NT), 0, s, C, B);
+}
+
+template <typename real>
+hipError_t launch_step2d_batch(const Coef<real>& C, const BatchArgs<real>& B, int ntiles,
+                               int variant, hipStream_t s) {
+    if (ntiles <= 0) return hipSuccess;
+    switch (variant) {
+    case 0: launch_b<real, 0>(C, B, ntiles, s); break;
+    case 1: launch_b<real, 1>(C, B, ntiles, s); break;
+    case 2: launch_b<real, 2>(C, B, ntiles, s); break;
+    default:
+        if constexpr (Variants2D<real>::count > 3) {
+            if (variant == 3) launch_b<real, 3>(C, B, ntiles, s);
+            else if (variant == 4) launch_b<real, 4>(C, B, ntiles, s);
+            else if (variant == 5) launch_b<real, 5>(C, B, ntiles, s);
+            else return hipErrorInvalidValue;
+        } else {
+            return hipErrorInvalidValue;
+        }
+    }
+    return hipGetLastError();
+}
+
+template int tile2d_variants<float>();
+template int tile2d_variants<double>();
+template void tile2d_shape<float>(int, int*, int*);
+template void tile2d_shape<double>(int, int*, int*);
+template hipError_t launch_step2d_batch<float>(const Coef<float>&, const BatchArgs<float>&, int,
+                                               int, hipStream_t);
+template hipError_t launch_step2d_batch<double>(const Coef<double>&, const BatchArgs<double>&,
+                                                int, int, hipStream_t);
 template int step2d_variants<float>();
 template int step2d_variants<double>();
 template int grid2d_blocks<float>(int, int, int);

@@ -82,6 +82,20 @@ def lib():
             "lbm_set_variant": (C.c_int, [vp, C.c_int32]),
             "lbm_get_variant": (C.c_int, [vp, C.POINTER(C.c_int32)]),
             "lbm_autotune": (C.c_int, [vp, i64, vp, C.POINTER(C.c_int32), dp]),
+            "lbm_set_graph_steps": (C.c_int, [vp, i64]),
+            "lbm_batch_workspace_bytes": (C.c_size_t, [P, C.c_int32, C.POINTER(C.c_int32),
+                                                       C.POINTER(C.c_int32), C.POINTER(i64)]),
+            "lbm_create_batch": (C.c_int, [P, C.c_int32, C.POINTER(C.c_int32),
+                                           C.POINTER(C.c_int32), C.POINTER(i64), vp, vp,
+                                           C.c_size_t, C.POINTER(vp)]),
+            "lbm_batch_cases": (C.c_int, [vp, C.POINTER(C.c_int32)]),
+            "lbm_set_geometry_case": (C.c_int, [vp, C.c_int32, C.POINTER(C.c_uint8)]),
+            "lbm_wall_nodes_case": (C.c_int, [vp, C.c_int32, C.POINTER(C.c_int64),
+                                              C.POINTER(C.c_int64)]),
+            "lbm_set_wetting_case": (C.c_int, [vp, C.c_int32, vp, vp, C.c_double, C.c_double]),
+            "lbm_set_fields_case": (C.c_int, [vp, C.c_int32, vp, vp]),
+            "lbm_get_fields_case": (C.c_int, [vp, C.c_int32, vp, vp, vp]),
+            "lbm_get_diagnostics_case": (C.c_int, [vp, C.c_int32, C.POINTER(lbm_diag)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -221,6 +235,76 @@ def lbm_autotune(ctx, steps, save=None, nvariants=None):
     return best.value, (list(ms) if ms is not None else None)
 
 
+def lbm_set_graph_steps(ctx, steps):
+    _check(lib().lbm_set_graph_steps(ctx, int(steps)), "lbm_set_graph_steps")
+
+
+def _i32(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def _i64(a):
+    a = np.ascontiguousarray(a, dtype=np.int64)
+    return a, a.ctypes.data_as(C.POINTER(C.c_int64))
+
+
+def lbm_batch_workspace_bytes(p, nx, ny, n_wall_max):
+    ax, px = _i32(nx)
+    ay, py = _i32(ny)
+    aw, pw = _i64(n_wall_max)
+    return lib().lbm_batch_workspace_bytes(C.byref(p), len(ax), px, py, pw)
+
+
+def lbm_create_batch(p, nx, ny, n_wall_max, stream, workspace):
+    ax, px = _i32(nx)
+    ay, py = _i32(ny)
+    aw, pw = _i64(n_wall_max)
+    ctx = C.c_void_p()
+    _check(lib().lbm_create_batch(C.byref(p), len(ax), px, py, pw, C.c_void_p(stream),
+                                  _ptr(workspace), workspace.numel(), C.byref(ctx)),
+           "lbm_create_batch")
+    return ctx
+
+
+def lbm_set_geometry_case(ctx, i, solid):
+    s = np.ascontiguousarray(np.asarray(solid, dtype=np.uint8).ravel())
+    _check(lib().lbm_set_geometry_case(ctx, int(i), s.ctypes.data_as(C.POINTER(C.c_uint8))),
+           "lbm_set_geometry_case")
+
+
+def lbm_wall_nodes_case(ctx, i):
+    n = C.c_int64()
+    _check(lib().lbm_wall_nodes_case(ctx, int(i), None, C.byref(n)), "lbm_wall_nodes_case")
+    idx = np.zeros(max(n.value, 1), dtype=np.int64)
+    _check(lib().lbm_wall_nodes_case(ctx, int(i), idx.ctypes.data_as(C.POINTER(C.c_int64)),
+                                     C.byref(n)), "lbm_wall_nodes_case")
+    return idx[:n.value]
+
+
+def lbm_set_wetting_case(ctx, i, phi=None, drho=None, phi0=1.0, drho0=0.0):
+    _check(lib().lbm_set_wetting_case(ctx, int(i), _ptr(phi), _ptr(drho), float(phi0),
+                                      float(drho0)), "lbm_set_wetting_case")
+
+
+def lbm_set_fields_case(ctx, i, rho, u=None):
+    _check(lib().lbm_set_fields_case(ctx, int(i), _ptr(rho), _ptr(u)), "lbm_set_fields_case")
+
+
+def lbm_get_fields_case(ctx, i, rho=None, u=None, f=None):
+    _check(lib().lbm_get_fields_case(ctx, int(i), _ptr(rho), _ptr(u), _ptr(f)),
+           "lbm_get_fields_case")
+
+
+def lbm_get_diagnostics_case(ctx, i):
+    d = lbm_diag()
+    rc = lib().lbm_get_diagnostics_case(ctx, int(i), C.byref(d))
+    if rc not in (LBM_OK, LBM_EDOMAIN):
+        _check(rc, "lbm_get_diagnostics_case")
+    return rc, dict(mass=d.mass, max_u=d.max_u, rho_min=d.rho_min, rho_max=d.rho_max,
+                    flag=d.flag, n_fluid=d.n_fluid)
+
+
 # ---------------------------------------------------------------- helpers
 def make_params(lattice=9, precision=4, nx=64, ny=64, nz=1, tau=1.0, eos=LBM_EOS_CS,
                 a=1.0, b=4.0, R=1.0, T=None, T_ratio=0.75, omega=0.344, G=-1.0, sigma=0.0,
@@ -326,6 +410,108 @@ class Solver:
         saved and restored around the trials."""
         save = torch.empty(self.Q * self.N, dtype=self.dtype, device=self.device)
         nv = lbm_variant_count(self.p.lattice, self.p.precision) if report else None
+        best, ms = lbm_autotune(self.ctx, steps, save, nv)
+        torch.cuda.synchronize(self.device)
+        return (best, ms) if report else best
+
+    @property
+    def variant(self):
+        return lbm_get_variant(self.ctx)
+
+    @variant.setter
+    def variant(self, v):
+        lbm_set_variant(self.ctx, v)
+
+    def set_graph_steps(self, steps):
+        lbm_set_graph_steps(self.ctx, steps)
+
+
+class BatchSolver:
+    """Many independent D2Q9 lattices advanced together (one launch per
+    step, optionally replayed from a HIP graph)."""
+
+    def __init__(self, params, sizes, n_wall_max, device="cuda:0", stream=None):
+        self.p = params
+        self.device = torch.device(device)
+        self.dtype = torch.float32 if params.precision == 4 else torch.float64
+        self.sizes = [(int(a), int(b)) for a, b in sizes]
+        nx = [a for a, _ in self.sizes]
+        ny = [b for _, b in self.sizes]
+        nbytes = lbm_batch_workspace_bytes(params, nx, ny, n_wall_max)
+        if nbytes == 0:
+            raise LBMError(LBM_EINVAL, "lbm_batch_workspace_bytes", lib().lbm_last_error().decode())
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ctx = lbm_create_batch(params, nx, ny, n_wall_max, self.stream.cuda_stream, self.ws)
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            lbm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __len__(self):
+        return len(self.sizes)
+
+    def set_geometry(self, i, solid):
+        lbm_set_geometry_case(self.ctx, i, solid)
+
+    def wall_nodes(self, i):
+        return lbm_wall_nodes_case(self.ctx, i)
+
+    def set_scheme(self, scheme, scalar=0.0, phi0=1.0, drho0=0.0):
+        lbm_set_wetting(self.ctx, scheme, scalar, None, None, phi0, drho0)
+
+    def set_wetting(self, i, phi=None, drho=None, phi0=1.0, drho0=0.0):
+        lbm_set_wetting_case(self.ctx, i, phi, drho, phi0, drho0)
+
+    def set_fields(self, i, rho, u=None):
+        rho = torch.as_tensor(rho, dtype=self.dtype, device=self.device).contiguous().view(-1)
+        if u is not None:
+            u = torch.as_tensor(u, dtype=self.dtype, device=self.device).contiguous().view(-1)
+        lbm_set_fields_case(self.ctx, i, rho, u)
+        self._keep.append((rho, u))
+
+    def step(self, n):
+        lbm_step(self.ctx, n)
+
+    def step_timed(self, n):
+        return lbm_step_timed(self.ctx, n)
+
+    def set_graph_steps(self, steps):
+        lbm_set_graph_steps(self.ctx, steps)
+
+    def get_fields(self, i, rho=True, u=True, f=False):
+        nx, ny = self.sizes[i]
+        N = nx * ny
+        r = torch.empty(N, dtype=self.dtype, device=self.device) if rho else None
+        v = torch.empty(2 * N, dtype=self.dtype, device=self.device) if u else None
+        g = torch.empty(9 * N, dtype=self.dtype, device=self.device) if f else None
+        lbm_get_fields_case(self.ctx, i, r, v, g)
+        out = {}
+        if rho:
+            out["rho"] = r
+        if u:
+            out["u"] = v.view(2, N)
+        if f:
+            out["f"] = g.view(9, N)
+        return out
+
+    def diagnostics(self, i=None):
+        if i is None:
+            return lbm_get_diagnostics(self.ctx)
+        return lbm_get_diagnostics_case(self.ctx, i)
+
+    def autotune(self, steps=10, report=False):
+        nb = sum(9 * a * b for a, b in self.sizes) + 64 * len(self.sizes)
+        save = torch.empty(nb, dtype=self.dtype, device=self.device)
+        nv = lbm_variant_count(9, self.p.precision) if report else None
         best, ms = lbm_autotune(self.ctx, steps, save, nv)
         torch.cuda.synchronize(self.device)
         return (best, ms) if report else best

@@ -1,0 +1,150 @@
+"""Multi-case contexts and HIP-graph replay.
+
+The per-node arithmetic does not depend on how the lattice is cut into
+tiles, so a case advanced inside a multi-case context must be bitwise equal
+to the same case advanced alone, and graph replay must be bitwise equal to
+plain launches.
+"""
+import numpy as np
+import pytest
+
+from cases import Setup, lib_params
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [(70, 50), (128, 128), (33, 91), (200, 64), (17, 13)]
+
+
+def _case_dicts(precision):
+    out = []
+    for k, (nx, ny) in enumerate(SIZES):
+        R = max(2, min(nx, ny) // 6)
+        r0 = max(2, R * 0.8)
+        cx, cy = nx // 2, ny // 3
+        out.append(dict(nx=nx, ny=ny, geometry=("disk", (cx, cy), R),
+                        init=("droplet", (cx, cy + R + r0), r0), scheme="ivd",
+                        phi=1.0 + 0.1 * k, drho=0.002 * (k % 2), noise=1e-6, seed=20 + k,
+                        precision=precision))
+    return out
+
+
+def _single(L, s, steps, graph=0):
+    import torch
+    p = lib_params(L, s.op, s.case)
+    sol = L.Solver(p, max(len(s.walls), 1))
+    sol.set_geometry(s.solid)
+    w = sol.wall_nodes()
+    sol.set_wetting(0, 0.0, torch.as_tensor(s.phi_field.ravel()[w], dtype=sol.dtype, device="cuda"),
+                    torch.as_tensor(s.drho_field.ravel()[w], dtype=sol.dtype, device="cuda"))
+    sol.set_fields(s.rho0.ravel())
+    if graph:
+        sol.set_graph_steps(graph)
+    sol.step(steps)
+    return sol
+
+
+def _batch(L, setups, steps, graph=0, variant=None):
+    import torch
+    p = lib_params(L, setups[0].op, setups[0].case)
+    sizes = [(s.case["nx"], s.case["ny"]) for s in setups]
+    b = L.BatchSolver(p, sizes, [max(len(s.walls), 1) for s in setups])
+    b.set_scheme(0)
+    for i, s in enumerate(setups):
+        b.set_geometry(i, s.solid)
+        w = b.wall_nodes(i)
+        assert np.array_equal(w, s.walls)
+        b.set_wetting(i, torch.as_tensor(s.phi_field.ravel()[w], dtype=b.dtype, device="cuda"),
+                      torch.as_tensor(s.drho_field.ravel()[w], dtype=b.dtype, device="cuda"))
+        b.set_fields(i, s.rho0.ravel())
+    if variant is not None:
+        b.variant = variant
+    if graph:
+        b.set_graph_steps(graph)
+    b.step(steps)
+    return b
+
+
+@pytest.mark.parametrize("precision", [4, 8])
+def test_batch_equals_single_bitwise(oracle_mod, gpu_lib, precision):
+    import torch
+    setups = [Setup(oracle_mod, c) for c in _case_dicts(precision)]
+    b = _batch(gpu_lib, setups, 120)
+    for i, s in enumerate(setups):
+        one = _single(gpu_lib, s, 120)
+        a = b.get_fields(i, f=True)
+        c = one.get_fields(f=True)
+        torch.cuda.synchronize()
+        for key in ("rho", "u", "f"):
+            assert torch.equal(a[key], c[key]), (i, key)
+
+
+@pytest.mark.parametrize("variant", range(3))  # the FP64 tile shapes
+def test_batch_every_tile_shape_vs_oracle(oracle_mod, gpu_lib, variant):
+    setups = [Setup(oracle_mod, c) for c in _case_dicts(8)]
+    b = _batch(gpu_lib, setups, 80, variant=variant)
+    for i, s in enumerate(setups):
+        f = oracle_mod.run(s.op, s.solid, s.f0, 80, s.phi, s.drho)
+        rho_o, u_o, _ = oracle_mod.fields(s.op, s.solid, f, s.phi, s.drho)
+        out = b.get_fields(i)
+        err = np.abs(out["rho"].cpu().numpy() - rho_o).max()
+        uerr = np.abs(out["u"].cpu().numpy() - u_o).max()
+        assert err <= 1e-12 and uerr <= 1e-12, (i, err, uerr)
+
+
+def test_batch_diagnostics_are_case_totals(oracle_mod, gpu_lib):
+    setups = [Setup(oracle_mod, c) for c in _case_dicts(8)]
+    b = _batch(gpu_lib, setups, 30)
+    rc, tot = b.diagnostics()
+    assert rc == 0
+    parts = [b.diagnostics(i)[1] for i in range(len(setups))]
+    assert tot["n_fluid"] == sum(p["n_fluid"] for p in parts)
+    assert abs(tot["mass"] - sum(p["mass"] for p in parts)) <= 1e-12 * tot["mass"]
+    assert tot["max_u"] == max(p["max_u"] for p in parts)
+    for i, s in enumerate(setups):
+        f = oracle_mod.run(s.op, s.solid, s.f0, 30, s.phi, s.drho)
+        rho_o, _, _ = oracle_mod.fields(s.op, s.solid, f, s.phi, s.drho)
+        fl = s.solid.ravel() == 0
+        assert abs(parts[i]["mass"] - rho_o[fl].sum()) <= 1e-11 * rho_o[fl].sum()
+
+
+@pytest.mark.parametrize("kind", ["single", "batch"])
+def test_graph_replay_equals_eager(oracle_mod, gpu_lib, kind):
+    """Graph replays, with eager work and host syncs between them, give the
+    same bits as plain launches; an odd remainder runs eagerly."""
+    import torch
+    setups = [Setup(oracle_mod, c) for c in _case_dicts(4)]
+
+    def make(graph):
+        if kind == "single":
+            return _single(gpu_lib, setups[1], 0, graph=graph)
+        return _batch(gpu_lib, setups, 0, graph=graph)
+
+    def state(x):
+        if kind == "single":
+            return x.get_fields(f=True)["f"].clone()
+        return torch.cat([x.get_fields(i, f=True)["f"].view(-1) for i in range(len(setups))])
+
+    eager, graphed = make(0), make(10)
+    for chunk in (40, 20, 25, 10, 3):
+        eager.step(chunk)
+        graphed.step(chunk)
+        torch.cuda.synchronize()
+        a, g = state(eager), state(graphed)
+        # unrelated eager work on the same stream between replays
+        junk = torch.randn(1 << 16, device="cuda").sum()
+        torch.cuda.synchronize()
+        assert torch.equal(a, g), chunk
+    assert torch.isfinite(junk)
+
+
+def test_graph_recaptured_after_scheme_change(oracle_mod, gpu_lib):
+    import torch
+    s = Setup(oracle_mod, _case_dicts(8)[1])
+    a = _single(gpu_lib, s, 0, graph=8)
+    b = _single(gpu_lib, s, 0, graph=0)
+    for sol in (a, b):
+        sol.step(16)
+        sol.set_wetting(1, 0.1)  # constant virtual density from here on
+        sol.step(16)
+    torch.cuda.synchronize()
+    assert torch.equal(a.get_fields(f=True)["f"], b.get_fields(f=True)["f"])
