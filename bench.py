@@ -168,6 +168,48 @@ def run_c3(L, W, steps, warmup, graph_steps=50):
                 ratio=t_single / t_batch, graph_steps=graph_steps)
 
 
+def run_c4(L, W, T=1000, K=50):
+    """Adjoint workload: D2Q9 FP32 256^2, cylinder R = 40, droplet r = 32 on
+    top, per-wall parameters at phi = 1, drho = 0.  Times the forward step,
+    the checkpointed forward, and the full adjoint (recompute included); the
+    adjoint step time is the adjoint total minus the recomputed forward
+    steps, per step."""
+    import numpy as np
+    import torch
+    p = L.make_params(lattice=9, precision=4, nx=256, ny=256, T_ratio=0.75,
+                      sigma=W.SIGMA[("cs", 0.75, 9)], tau=1.0)
+    d = W.c4_adjoint(p.rho_g, p.rho_l)
+    s, nw = setup_solver(L, W, p, d, int(d["solid"].sum()))
+    s.step(50)
+    fwd_ms = s.step_timed(T) / T
+    s.set_fields(d["rho"].ravel())
+    ckpt = s.ckpt_buffer(T, K)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step_ckpt(T, K, ckpt)
+    torch.cuda.synchronize()
+    ckpt_ms = (time.perf_counter() - t0) * 1e3
+    rho_T = s.get_fields(rho=True, u=False)["rho"]
+    fluid = torch.as_tensor(d["solid"].ravel() == 0, device="cuda")
+    seed = torch.where(fluid, 2.0 * (rho_T - 0.5 * (p.rho_g + p.rho_l)), torch.zeros_like(rho_T))
+    s.adjoint(seed, T, K, ckpt)  # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gp, gd = s.adjoint(seed, T, K, ckpt)
+    torch.cuda.synchronize()
+    adj_ms = (time.perf_counter() - t0) * 1e3
+    nseg = (T + K - 1) // K
+    recompute = T - nseg
+    adj_step_ms = (adj_ms - recompute * fwd_ms) / T
+    s.close()
+    return dict(T=T, K=K, wall_nodes=nw, forward_step_ms=round(fwd_ms, 5),
+                adjoint_step_ms=round(adj_step_ms, 5),
+                adjoint_step_over_forward=round(adj_step_ms / fwd_ms, 3),
+                backward_total_ms=round(adj_ms, 3), checkpointed_forward_ms=round(ckpt_ms, 3),
+                backward_over_forward=round(adj_ms / (fwd_ms * T), 3),
+                grad_finite=bool(torch.isfinite(gp).all() and torch.isfinite(gd).all()))
+
+
 def cpu_baseline(data, lbm_params, steps):
     """The CPU oracle (FP64) on the same 2048^2 lattice and initial state,
     `steps` steps."""
@@ -273,6 +315,9 @@ def main():
         out["secondary"]["batched_96_cases_fp32"] = {k: (round(v, 3) if isinstance(v, float) else v)
                                                      for k, v in c3.items()}
         log(f"C3: {out['secondary']['batched_96_cases_fp32']}")
+        log("C4: adjoint of the 256^2 D2Q9 FP32 workload, T = 1000, K = 50")
+        out["secondary"]["adjoint_256_fp32"] = run_c4(L, W)
+        log(f"C4: {out['secondary']['adjoint_256_fp32']}")
 
     if not args.no_cpu_baseline:
         log(f"CPU oracle: {args.cpu_steps} steps of the 2048^2 workload")

@@ -258,6 +258,33 @@ int lbm_set_fields_case(lbm_ctx* ctx, int32_t i, const void* rho_dev, const void
 int lbm_get_fields_case(lbm_ctx* ctx, int32_t i, void* rho_dev, void* u_dev, void* f_dev);
 int lbm_get_diagnostics_case(lbm_ctx* ctx, int32_t i, lbm_diag* host_out);
 
+/* ------------------------------------------------------------ adjoint */
+/* Discrete adjoint of the D2Q9 step (single lattices), for gradients of a
+ * loss on the state at time T with respect to the per-wall-node parameters
+ * phi_b, drho_b of the improved virtual-density scheme (Eq. 16).
+ *
+ * lbm_step_ckpt: advance T steps like lbm_step, storing the state at times
+ * 0, K, 2K, ... (< T) into ckpt_dev (caller-owned device memory of
+ * ceil(T/K) * Q*N reals).
+ *
+ * lbm_adjoint: with the checkpoints of that run (taken under the same
+ * geometry and wetting parameters), computes
+ *   seed_kind 0: seed_dev = dL/drho(T) (N reals; only fluid entries used),
+ *   seed_kind 1: seed_dev = dL/df(T) (Q*N reals),
+ * and writes dL/dphi and dL/ddrho (wall-list order, ctx precision; each
+ * nullable) and, if lam0_dev != NULL, dL/df(0) (Q*N reals, 0 on solid).
+ * Each segment of K steps is recomputed from its checkpoint into the
+ * workspace, then the steps are transposed in reverse order.  work_dev:
+ * caller-owned device memory of at least lbm_adjoint_workspace_bytes(ctx,
+ * K) bytes.  The context state is not changed.  Gradients through the
+ * clamp of the limiter are taken as 1 on the closed interval
+ * [rho_g, rho_l] and 0 outside. */
+size_t lbm_adjoint_workspace_bytes(lbm_ctx* ctx, int64_t K);
+int lbm_step_ckpt(lbm_ctx* ctx, int64_t T, int64_t K, void* ckpt_dev);
+int lbm_adjoint(lbm_ctx* ctx, int32_t seed_kind, const void* seed_dev, int64_t T, int64_t K,
+                const void* ckpt_dev, void* work_dev, size_t work_bytes, void* grad_phi_dev,
+                void* grad_drho_dev, void* lam0_dev);
+
 #ifdef __cplusplus
 }
 #endif

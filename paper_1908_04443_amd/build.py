@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "liblbm.so")
 BUILD = os.path.join(HERE, "_build")
 
 SOURCES = ["api.cpp", "thermo.cpp", "geometry.cpp", "step2d.hip", "step_march.hip",
-           "aux.hip"]
+           "aux.hip", "adjoint2d.hip"]
 EXTRA_SOURCES = []
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

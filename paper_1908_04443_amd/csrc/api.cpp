@@ -446,6 +446,89 @@ static int upload_cases(lbm_ctx* c) {
     return LBM_OK;
 }
 
+// ---- adjoint workspace: K segment states, ping-pong lam (partial + ext),
+// per-node gather inputs, gradient scratch
+struct AdjLayout {
+    size_t seg, lam0, lam1, ext0, ext1, sb, gphi, gdrho, total;
+};
+static AdjLayout adj_layout(const lbm_ctx* c, int64_t K) {
+    AdjLayout L{};
+    const size_t s = (size_t)c->prec, N = (size_t)c->N;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        off = (off + 255) & ~size_t(255);
+        size_t o = off;
+        off += bytes;
+        return o;
+    };
+    L.seg = take((size_t)K * 9 * N * s);
+    L.lam0 = take(9 * N * s);
+    L.lam1 = take(9 * N * s);
+    L.ext0 = take(N * s);
+    L.ext1 = take(N * s);
+    L.sb = take(4 * N * s);
+    const size_t nw = c->geom.walls.empty() ? 1 : c->geom.walls.size();
+    L.gphi = take(nw * s);
+    L.gdrho = take(nw * s);
+    L.total = (off + 255) & ~size_t(255);
+    return L;
+}
+
+// one forward step from fin to fout (same kernels as lbm_step)
+template <typename real>
+static hipError_t step_from(lbm_ctx* c, const Coef<real>& C, const void* fin, void* fout) {
+    Fields<real> F = make_fields<real>(c, c->cur);
+    F.fin = (const real*)fin;
+    F.fout = (real*)fout;
+    FieldOut<real> O{nullptr, nullptr, nullptr};
+    return launch_step2d<real>(C, F, O, MODE_STEP, c->variant, c->stream);
+}
+
+template <typename real>
+static int run_adjoint(lbm_ctx* c, int kind, const void* seed, int64_t T, int64_t K,
+                       const void* ckpt, char* work, void* gphi, void* gdrho, void* lam0) {
+    const AdjLayout Lw = adj_layout(c, K);
+    const uint32_t N = (uint32_t)c->N;
+    const size_t state = (size_t)9 * N * sizeof(real);
+    const int64_t nw = (int64_t)c->geom.walls.size();
+    real* gp = gphi ? (real*)gphi : (real*)(work + Lw.gphi);
+    real* gd = gdrho ? (real*)gdrho : (real*)(work + Lw.gdrho);
+    LBM_HIP(launch_fill<real>(gp, real(0), nw, c->stream));
+    LBM_HIP(launch_fill<real>(gd, real(0), nw, c->stream));
+    real* lam[2] = {(real*)(work + Lw.lam0), (real*)(work + Lw.lam1)};
+    real* ext[2] = {(real*)(work + Lw.ext0), (real*)(work + Lw.ext1)};
+    char* seg = work + Lw.seg;
+    LBM_HIP(launch_adj_seed<real>(kind, c->cls, (const real*)seed, lam[0], ext[0], N, c->stream));
+    int cur = 0;
+    const Coef<real> C = make_coef<real>(c);
+    const int64_t nseg = (T + K - 1) / K;
+    for (int64_t sg = nseg - 1; sg >= 0; --sg) {
+        const int64_t len = (T - sg * K) < K ? (T - sg * K) : K;
+        // restore the checkpoint and recompute the segment's states
+        LBM_HIP(hipMemcpyAsync(seg, (const char*)ckpt + (size_t)sg * state, state,
+                               hipMemcpyDeviceToDevice, c->stream));
+        for (int64_t i = 1; i < len; ++i)
+            LBM_HIP(step_from<real>(c, C, seg + (size_t)(i - 1) * state, seg + (size_t)i * state));
+        for (int64_t i = len - 1; i >= 0; --i) {
+            Fields<real> F = make_fields<real>(c, c->cur);
+            F.fin = (const real*)(seg + (size_t)i * state);
+            F.fout = nullptr;
+            AdjArgs<real> A;
+            A.lam_in = lam[cur];
+            A.ext_in = ext[cur];
+            A.lam_out = lam[cur ^ 1];
+            A.ext_out = ext[cur ^ 1];
+            A.sb = (real*)(work + Lw.sb);
+            A.grad_phi = gp;
+            A.grad_drho = gd;
+            LBM_HIP(launch_adjoint2d<real>(C, F, A, c->stream));
+            cur ^= 1;
+        }
+    }
+    if (lam0)
+        LBM_HIP(launch_adj_finish<real>(c->cls, lam[cur], ext[cur], (real*)lam0, N, c->stream));
+    return LBM_OK;
+}
 }  // namespace lbm
 
 using namespace lbm;
@@ -1037,6 +1120,48 @@ int lbm_set_graph_steps(lbm_ctx* c, int64_t steps) {
     c->graph_steps = (steps + 1) / 2 * 2;  // even: a replay keeps the buffer parity
     c->graph_dirty = true;
     return LBM_OK;
+}
+
+size_t lbm_adjoint_workspace_bytes(lbm_ctx* c, int64_t K) {
+    if (!c || K < 1 || c->is_batch || c->p.lattice != 9) return 0;
+    return adj_layout(c, K).total;
+}
+
+int lbm_step_ckpt(lbm_ctx* c, int64_t T, int64_t K, void* ckpt_dev) {
+    if (!c || !ckpt_dev) return fail(LBM_EINVAL, "NULL argument");
+    if (T < 0 || K < 1) return fail(LBM_EINVAL, "need T >= 0 and K >= 1");
+    if (c->is_batch) return fail(LBM_EINVAL, "checkpointed stepping is for single lattices");
+    if (!ready(c)) return fail(LBM_ESTATE, "geometry and fields must be set");
+    if (c->domain_error) return fail(LBM_EDOMAIN, "a previous step left the psi domain");
+    const size_t state = (size_t)c->Q * c->N * c->prec;
+    for (int64_t t = 0, sg = 0; t < T; t += K, ++sg) {
+        LBM_HIP(hipMemcpyAsync((char*)ckpt_dev + (size_t)sg * state, c->f[c->cur], state,
+                               hipMemcpyDeviceToDevice, c->stream));
+        const int64_t n = (T - t) < K ? (T - t) : K;
+        int rc = c->prec == 4 ? run_steps<float>(c, n) : run_steps<double>(c, n);
+        if (rc != LBM_OK) return rc;
+    }
+    return LBM_OK;
+}
+
+int lbm_adjoint(lbm_ctx* c, int32_t seed_kind, const void* seed_dev, int64_t T, int64_t K,
+                const void* ckpt_dev, void* work_dev, size_t work_bytes, void* grad_phi_dev,
+                void* grad_drho_dev, void* lam0_dev) {
+    if (!c || !seed_dev || !ckpt_dev || !work_dev) return fail(LBM_EINVAL, "NULL argument");
+    if (c->is_batch || c->p.lattice != 9)
+        return fail(LBM_EINVAL, "the adjoint is implemented for single D2Q9 lattices");
+    if (seed_kind != 0 && seed_kind != 1) return fail(LBM_EINVAL, "seed_kind must be 0 or 1");
+    if (T < 1 || K < 1) return fail(LBM_EINVAL, "need T >= 1 and K >= 1");
+    if (!c->have_geom) return fail(LBM_ESTATE, "no geometry set");
+    if (c->domain_error) return fail(LBM_EDOMAIN, "a previous step left the psi domain");
+    const size_t need = adj_layout(c, K).total;
+    if (work_bytes < need)
+        return fail(LBM_ENOMEM, "adjoint workspace needs " + std::to_string(need) + " bytes");
+    if (((uintptr_t)work_dev & 255) != 0) return fail(LBM_EINVAL, "workspace must be 256-byte aligned");
+    return c->prec == 4 ? run_adjoint<float>(c, seed_kind, seed_dev, T, K, ckpt_dev, (char*)work_dev,
+                                             grad_phi_dev, grad_drho_dev, lam0_dev)
+                        : run_adjoint<double>(c, seed_kind, seed_dev, T, K, ckpt_dev,
+                                              (char*)work_dev, grad_phi_dev, grad_drho_dev, lam0_dev);
 }
 
 }  // extern "C"

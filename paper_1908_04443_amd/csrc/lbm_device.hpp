@@ -363,6 +363,130 @@ __device__ __forceinline__ void collide(const Coef<real>& C, const real* f, real
     }
 }
 
+// dp/drho of the equation of state
+template <typename real>
+__device__ __forceinline__ real eos_dp(const Coef<real>& C, real rho) {
+    if (C.eos == EOS_CS) {
+        // d(rho Z)/drho of Carnahan-Starling = (1 + 4h + 4h^2 - 4h^3 + h^4) / (1 - h)^4
+        const real h = C.eos_b * real(0.25) * rho;
+        const real om = real(1) - h;
+        const real om2 = om * om;
+        const real num = real(1) + real(4) * h + real(4) * h * h - real(4) * h * h * h + h * h * h * h;
+        return C.eos_RT * num / (om2 * om2) - real(2) * C.eos_a * rho;
+    } else {
+        const real br = C.eos_b * rho;
+        const real om = real(1) - br;
+        const real D = real(1) + real(2) * br - br * br;
+        const real Dp = real(2) * C.eos_b - real(2) * C.eos_b * br;
+        return C.eos_RT / (om * om) - C.eos_aphi * (real(2) * rho * D - rho * rho * Dp) / (D * D);
+    }
+}
+
+// dpsi/drho for psi = sqrt(2 (p - rho/3) / G) (Eq. 6); 0 where psi = 0
+template <typename real>
+__device__ __forceinline__ real dpsi_drho(const Coef<real>& C, real rho, real psi) {
+    if (!(psi > real(0))) return real(0);
+    return C.two_over_G * (eos_dp(C, rho) - real(1.0 / 3.0)) / (real(2) * psi);
+}
+
+// Vector-Jacobian product of the collision of one fluid node (D2Q9), the
+// transpose of collide(): given lam = d L / d f* (post-collision), returns
+// gf = d L / d f through the moments, and the adjoints of the node's
+// density (rho_bar, all explicit paths: m_eq, u), total force (F_bar) and
+// of the cohesive force and own psi that enter Eq. 7's sigma term.
+template <typename real>
+__device__ __forceinline__ void collide_vjp_d2q9(const Coef<real>& C, const real* f, real rho,
+                                                 const real* F, const real* Fm, real psi,
+                                                 const real* lam, real* gf, real& rho_bar,
+                                                 real* F_bar, real* Fm_bar, real& psi_bar) {
+    using L = D2Q9;
+    constexpr int Q = 9;
+    // moments and velocity (forward)
+    real m[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        real s = real(0);
+#pragma unroll
+        for (int a = 0; a < Q; ++a)
+            if (L::M[k][a] != 0) s += real(L::M[k][a]) * f[a];
+        m[k] = s;
+    }
+    const real ux = (m[3] + real(0.5) * F[0]) / rho;
+    const real uy = (m[5] + real(0.5) * F[1]) / rho;
+    const real u2 = ux * ux + uy * uy;
+    // mu_k = d L / d m*_k = (1/norm_k) sum_a M_ka lam_a
+    real mu[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        real s = real(0);
+#pragma unroll
+        for (int a = 0; a < Q; ++a)
+            if (L::M[k][a] != 0) s += real(L::M[k][a]) * lam[a];
+        mu[k] = s * real(1.0 / L::norm[k]);
+    }
+    real sk[Q], hk[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        sk[k] = C.s[L::grp[k]];
+        hk[k] = real(1) - real(0.5) * sk[k];
+    }
+    // m* = m - s (m - m_eq(rho, u)) + h S(u, F, Fm, psi)
+    // d m_eq / d rho (at fixed u) and d m_eq / d u
+    const real dmr[Q] = {real(1), real(-2) + real(3) * u2, real(1) - real(3) * u2, ux, -ux, uy, -uy,
+                         ux * ux - uy * uy, ux * uy};
+    real ubx = real(0), uby = real(0), rb = real(0);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) rb += mu[k] * sk[k] * dmr[k];
+    // d m_eq/du: k=1: 6 rho u, k=2: -6 rho u, k=3: (rho,0), k=4: (-rho,0), k=5: (0,rho),
+    // k=6: (0,-rho), k=7: 2 rho (ux, -uy), k=8: rho (uy, ux)
+    const real e1 = mu[1] * sk[1] * real(6) * rho - mu[2] * sk[2] * real(6) * rho;
+    ubx += e1 * ux + (mu[3] * sk[3] - mu[4] * sk[4]) * rho + mu[7] * sk[7] * real(2) * rho * ux +
+           mu[8] * sk[8] * rho * uy;
+    uby += e1 * uy + (mu[5] * sk[5] - mu[6] * sk[6]) * rho - mu[7] * sk[7] * real(2) * rho * uy +
+           mu[8] * sk[8] * rho * ux;
+    // source rows (Eq. 7): S1 = 6 u.F + ce sig, S2 = -6 u.F - ceps sig, S3 = Fx, S4 = -Fx,
+    // S5 = Fy, S6 = -Fy, S7 = 2 (ux Fx - uy Fy), S8 = ux Fy + uy Fx
+    const real a1 = mu[1] * hk[1] * real(6) - mu[2] * hk[2] * real(6);
+    ubx += a1 * F[0] + mu[7] * hk[7] * real(2) * F[0] + mu[8] * hk[8] * F[1];
+    uby += a1 * F[1] - mu[7] * hk[7] * real(2) * F[1] + mu[8] * hk[8] * F[0];
+    real Fbx = a1 * ux + mu[3] * hk[3] - mu[4] * hk[4] + mu[7] * hk[7] * real(2) * ux + mu[8] * hk[8] * uy;
+    real Fby = a1 * uy + mu[5] * hk[5] - mu[6] * hk[6] - mu[7] * hk[7] * real(2) * uy + mu[8] * hk[8] * ux;
+    // sigma term: sig = |Fm|^2 / psi^2
+    const real sg = mu[1] * hk[1] * C.sig_e - mu[2] * hk[2] * C.sig_eps;
+    if (psi > real(0)) {
+        const real ip2 = real(1) / (psi * psi);
+        Fm_bar[0] = sg * real(2) * Fm[0] * ip2;
+        Fm_bar[1] = sg * real(2) * Fm[1] * ip2;
+        psi_bar = -sg * real(2) * (Fm[0] * Fm[0] + Fm[1] * Fm[1]) * ip2 / psi;
+    } else {
+        Fm_bar[0] = Fm_bar[1] = real(0);
+        psi_bar = real(0);
+    }
+    // u = (j + F/2) / rho
+    const real jbx = ubx / rho, jby = uby / rho;
+    Fbx += real(0.5) * jbx;
+    Fby += real(0.5) * jby;
+    rb -= (ubx * ux + uby * uy) / rho;
+    // adjoint of m: direct (1 - s) part plus rho and j paths
+    real mb[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) mb[k] = mu[k] * (real(1) - sk[k]);
+    mb[0] += rb;
+    mb[3] += jbx;
+    mb[5] += jby;
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+        real s = real(0);
+#pragma unroll
+        for (int k = 0; k < Q; ++k)
+            if (L::M[k][a] != 0) s += real(L::M[k][a]) * mb[k];
+        gf[a] = s;
+    }
+    rho_bar = real(0);  // the density path is carried by mb[0] (rho = m_0 = sum f)
+    F_bar[0] = Fbx;
+    F_bar[1] = Fby;
+}
+
 template <typename L, typename real>
 __device__ __forceinline__ real feq(int a, real rho, const real* u) {
     real eu = real(L::ex[a]) * u[0] + real(L::ey[a]) * u[1];

@@ -124,6 +124,27 @@ template <typename real>
 hipError_t launch_step3d(const Coef<real>& C, const Fields<real>& F, const FieldOut<real>& O,
                          int mode, int variant, hipStream_t s);
 
+// discrete adjoint of the D2Q9 step (adjoint2d.hip)
+template <typename real>
+struct AdjArgs {
+    const real* lam_in;  // partial lam(t+1) [9][N]
+    const real* ext_in;  // density-path part of lam(t+1) [N]
+    real* lam_out;       // partial lam(t) [9][N]
+    real* ext_out;       // density-path part of lam(t) [N]
+    real* sb;            // per node: dL/dF_m x, y, psi, rho ([4][N])
+    real* grad_phi;      // per wall node (accumulated)
+    real* grad_drho;
+};
+template <typename real>
+hipError_t launch_adjoint2d(const Coef<real>& C, const Fields<real>& F, const AdjArgs<real>& A,
+                            hipStream_t s);
+template <typename real>
+hipError_t launch_adj_seed(int kind, const uint8_t* cls, const real* seed, real* lam, real* ext,
+                           uint32_t N, hipStream_t s);
+template <typename real>
+hipError_t launch_adj_finish(const uint8_t* cls, const real* lam, const real* ext, real* out,
+                             uint32_t N, hipStream_t s);
+
 // auxiliary kernels
 template <typename real>
 hipError_t launch_init_eq(int lattice, const uint8_t* cls, const real* rho, const real* u,

@@ -19,8 +19,7 @@
 // State: post-streaming populations, SoA f[a*N + n]; fin -> fout ping-pong.
 // Only fluid slots of fout are written; a population that would enter a
 // solid node is written back to its origin in the opposite direction.
-#include "lbm_device.hpp"
-#include "lbm_kernels.hpp"
+#include "tile2d.hpp"
 
 namespace lbm {
 
@@ -32,124 +31,16 @@ __device__ __forceinline__ void d2q9_tile(const Coef<real>& C, const Fields<real
                                           const FieldOut<real>& Out, const int nx, const int ny,
                                           const int x0, const int y0, const int part) {
     using L = D2Q9;
-    constexpr int LX = TX + 4, LY = TY + 4;  // tile + 2-node halo
+    constexpr int LX = TX + 4;
     constexpr int ROWS = NT / TX;
-    constexpr int RPT = TY / ROWS;  // owned nodes per thread
-    static_assert(NT % TX == 0 && TY % ROWS == 0, "tile shape");
-    constexpr int RING = 4 * LX + 4 * TY;
-
-    __shared__ uint8_t s_cls[LX * LY];
-    __shared__ real s_rho[LX * LY];
-    __shared__ real s_psi[LX * LY];
-    __shared__ uint32_t s_col[LX];  // wrapped x of each halo column
-    __shared__ uint32_t s_row[LY];  // wrapped y * nx of each halo row
-
+    constexpr int RPT = TY / ROWS;
+    __shared__ TileLDS<real, TX, TY> S;
     const uint32_t N = (uint32_t)nx * (uint32_t)ny;
     const PopIO<real, BUF> io(Fd.fin, Fd.fout, N, 9);
     const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
     bool bad = false;
-
-    for (int i = tid; i < LX + LY; i += NT) {
-        if (i < LX) s_col[i] = (uint32_t)wrapi(x0 - 2 + i, nx);
-        else s_row[i - LX] = (uint32_t)wrapi(y0 - 2 + (i - LX), ny) * (uint32_t)nx;
-    }
-    __syncthreads();
-    // node classes of the tile + 2 halo
-    for (int i = tid; i < LX * LY; i += NT) {
-        const int lx = i % LX, ly = i / LX;
-        s_cls[i] = Fd.cls[s_row[ly] + s_col[lx]];
-    }
-    __syncthreads();
-
-    // owned tile nodes: populations into registers, density into LDS
     real f[RPT][9];
-#pragma unroll
-    for (int k = 0; k < RPT; ++k) {
-        const int ly = ty + k * ROWS;
-        const int p = (ly + 2) * LX + tx + 2;
-        const uint32_t n = s_row[ly + 2] + s_col[tx + 2];
-        real r = real(0);
-        if (s_cls[p] == CLS_FLUID) {
-#pragma unroll
-            for (int a = 0; a < 9; ++a) f[k][a] = io.ld(a, n);
-            r = f[k][0];
-#pragma unroll
-            for (int a = 1; a < 9; ++a) r += f[k][a];
-        } else {
-#pragma unroll
-            for (int a = 0; a < 9; ++a) f[k][a] = real(0);
-        }
-        s_rho[p] = r;
-    }
-    // halo ring: density only
-    for (int j = tid; j < RING; j += NT) {
-        int lx, ly;
-        if (j < 2 * LX) {
-            ly = j / LX;
-            lx = j % LX;
-        } else if (j < 4 * LX) {
-            const int jj = j - 2 * LX;
-            ly = TY + 2 + jj / LX;
-            lx = jj % LX;
-        } else {
-            const int jj = j - 4 * LX;
-            ly = 2 + jj / 4;
-            const int c = jj % 4;
-            lx = c < 2 ? c : TX + c;
-        }
-        const int p = ly * LX + lx;
-        real r = real(0);
-        if (s_cls[p] == CLS_FLUID) {
-            const uint32_t n = s_row[ly] + s_col[lx];
-            r = io.ld(0, n);
-#pragma unroll
-            for (int a = 1; a < 9; ++a) r += io.ld(a, n);
-        }
-        s_rho[p] = r;
-    }
-    __syncthreads();
-
-    // psi on tile + 1 halo; wall nodes first get their virtual density
-    for (int i = tid; i < (TX + 2) * (TY + 2); i += NT) {
-        const int lx = 1 + i % (TX + 2), ly = 1 + i / (TX + 2);
-        const int p = ly * LX + lx;
-        const uint8_t c = s_cls[p];
-        real ps = real(0);
-        if (c == CLS_FLUID) {
-            ps = psi_of(C, s_rho[p], bad);
-        } else if (c == CLS_WALL) {
-            if (C.scheme == WET_IVD) {
-                // Eq. 17: w-weighted mean over the fluid neighbours
-                real num = real(0), den = real(0);
-                bool first = true;
-#pragma unroll
-                for (int a = 1; a < 9; ++a) {
-                    const int q = p + L::ex[a] + L::ey[a] * LX;
-                    if (s_cls[q] == CLS_FLUID) {
-                        const real w = real(L::w12[a]) * real(1.0 / 12.0);
-                        num = first ? w * s_rho[q] : num + w * s_rho[q];
-                        den = first ? w : den + w;
-                        first = false;
-                    }
-                }
-                const real rave = num / den;
-                const int kw = Fd.widx[s_row[ly] + s_col[lx]];
-                // Eq. 16 (phi scales, drho shifts) and the limiter
-                real rw = Fd.phi[kw] * rave - Fd.drho[kw];
-                rw = rw > C.rho_l ? C.rho_l : rw;
-                rw = rw < C.rho_g ? C.rho_g : rw;
-                s_rho[p] = rw;
-                ps = psi_of(C, rw, bad);
-            } else if (C.scheme == WET_VD) {
-                s_rho[p] = C.rho_w;
-                ps = C.psi_w;
-            } else {
-                s_rho[p] = real(0);
-            }
-        }
-        s_psi[p] = ps;
-    }
-    __syncthreads();
+    d2q9_prologue<real, TX, TY, NT, BUF>(C, Fd, io, nx, ny, x0, y0, S, f, bad);
 
     double d_sum = 0.0;
     real d_umax = real(0), d_rmin = real(1e30), d_rmax = real(-1e30);
@@ -161,11 +52,11 @@ __device__ __forceinline__ void d2q9_tile(const Coef<real>& C, const Fields<real
         const int gx = x0 + tx, gy = y0 + ly;
         if (gx >= nx || gy >= ny) continue;  // ragged tile: not owned
         const int p = (ly + 2) * LX + tx + 2;
-        const uint32_t n = s_row[ly + 2] + s_col[tx + 2];
-        const uint8_t c = s_cls[p];
+        const uint32_t n = S.row[ly + 2] + S.col[tx + 2];
+        const uint8_t c = S.cls[p];
         if (c != CLS_FLUID) {
             if (MODE == MODE_FIELDS) {
-                if (Out.rho) Out.rho[n] = (c == CLS_WALL) ? s_rho[p] : real(0);
+                if (Out.rho) Out.rho[n] = (c == CLS_WALL) ? S.rho[p] : real(0);
                 if (Out.u) {
                     Out.u[n] = real(0);
                     Out.u[(size_t)N + n] = real(0);
@@ -173,33 +64,10 @@ __device__ __forceinline__ void d2q9_tile(const Coef<real>& C, const Fields<real
             }
             continue;
         }
-        const real rho = s_rho[p];
-        const real psi_c = s_psi[p];
-        // Eq. 5 (and Eq. 8 for the solid-fluid interaction)
-        real smx = real(0), smy = real(0), sax = real(0), say = real(0);
-#pragma unroll
-        for (int a = 1; a < 9; ++a) {
-            const int q = p + L::ex[a] + L::ey[a] * LX;
-            const real w = real(L::w12[a]) * real(1.0 / 12.0);
-            const real wp = w * s_psi[q];
-            if (L::ex[a] == 1) smx += wp;
-            if (L::ex[a] == -1) smx -= wp;
-            if (L::ey[a] == 1) smy += wp;
-            if (L::ey[a] == -1) smy -= wp;
-            if (C.scheme == WET_SFI && s_cls[q] != CLS_FLUID) {
-                if (L::ex[a] == 1) sax += w;
-                if (L::ex[a] == -1) sax -= w;
-                if (L::ey[a] == 1) say += w;
-                if (L::ey[a] == -1) say -= w;
-            }
-        }
+        const real rho = S.rho[p];
+        const real psi_c = S.psi[p];
         real Fm[2], F[2];
-        Fm[0] = -C.G * psi_c * smx;
-        Fm[1] = -C.G * psi_c * smy;
-        const real fax = (C.scheme == WET_SFI) ? -C.G_w * rho * sax : real(0);
-        const real fay = (C.scheme == WET_SFI) ? -C.G_w * rho * say : real(0);
-        F[0] = Fm[0] + fax + C.body[0];
-        F[1] = Fm[1] + fay + C.body[1];
+        d2q9_force<real, LX>(C, S.cls, S.psi, p, rho, Fm, F);
 
         if (MODE == MODE_FIELDS) {
             const real jx = f[k][1] - f[k][3] + f[k][5] - f[k][6] - f[k][7] + f[k][8];
@@ -226,8 +94,8 @@ __device__ __forceinline__ void d2q9_tile(const Coef<real>& C, const Fields<real
 #pragma unroll
         for (int a = 0; a < 9; ++a) {
             const int q = p + L::ex[a] + L::ey[a] * LX;
-            if (s_cls[q] == CLS_FLUID) {
-                const uint32_t m = s_row[ly + 2 + L::ey[a]] + s_col[tx + 2 + L::ex[a]];
+            if (S.cls[q] == CLS_FLUID) {
+                const uint32_t m = S.row[ly + 2 + L::ey[a]] + S.col[tx + 2 + L::ex[a]];
                 io.st(a, m, fs[a]);
             } else {
                 io.st(L::opp[a], n, fs[a]);

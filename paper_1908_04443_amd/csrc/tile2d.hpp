@@ -1,0 +1,171 @@
+// tile2d.hpp -- the first half of the fused D2Q9 tile step, shared by the
+// step kernels and the adjoint's forward recompute: for a TX x TY tile at
+// (x0, y0) it loads node classes of the tile plus a 2-node halo, the
+// populations of the owned nodes into registers, the density of the tile
+// plus 2-node halo, the wall virtual densities (Eqs. 16-17 with the
+// limiter, the constant virtual density, or none for Eq. 8) and psi
+// (Eq. 6) on the tile plus a 1-node halo, all in LDS.
+#pragma once
+#include "lbm_device.hpp"
+#include "lbm_kernels.hpp"
+
+namespace lbm {
+
+template <typename real, int TX, int TY>
+struct TileLDS {
+    static constexpr int LX = TX + 4, LY = TY + 4;
+    uint8_t cls[LX * LY];
+    real rho[LX * LY];
+    real psi[LX * LY];
+    uint32_t col[LX];  // wrapped x of each halo column
+    uint32_t row[LY];  // wrapped y * nx of each halo row
+};
+
+template <typename real, int TX, int TY, int NT, bool BUF>
+__device__ __forceinline__ void d2q9_prologue(const Coef<real>& C, const Fields<real>& Fd,
+                                              const PopIO<real, BUF>& io, const int nx,
+                                              const int ny, const int x0, const int y0,
+                                              TileLDS<real, TX, TY>& S,
+                                              real (&f)[TY / (NT / TX)][9], bool& bad) {
+    using L = D2Q9;
+    constexpr int LX = TX + 4, LY = TY + 4;
+    constexpr int ROWS = NT / TX;
+    constexpr int RPT = TY / ROWS;
+    static_assert(NT % TX == 0 && TY % ROWS == 0, "tile shape");
+    constexpr int RING = 4 * LX + 4 * TY;
+    const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
+
+    for (int i = tid; i < LX + LY; i += NT) {
+        if (i < LX) S.col[i] = (uint32_t)wrapi(x0 - 2 + i, nx);
+        else S.row[i - LX] = (uint32_t)wrapi(y0 - 2 + (i - LX), ny) * (uint32_t)nx;
+    }
+    __syncthreads();
+    for (int i = tid; i < LX * LY; i += NT) {
+        const int lx = i % LX, ly = i / LX;
+        S.cls[i] = Fd.cls[S.row[ly] + S.col[lx]];
+    }
+    __syncthreads();
+
+    // owned tile nodes: populations into registers, density into LDS
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+        const int ly = ty + k * ROWS;
+        const int p = (ly + 2) * LX + tx + 2;
+        const uint32_t n = S.row[ly + 2] + S.col[tx + 2];
+        real r = real(0);
+        if (S.cls[p] == CLS_FLUID) {
+#pragma unroll
+            for (int a = 0; a < 9; ++a) f[k][a] = io.ld(a, n);
+            r = f[k][0];
+#pragma unroll
+            for (int a = 1; a < 9; ++a) r += f[k][a];
+        } else {
+#pragma unroll
+            for (int a = 0; a < 9; ++a) f[k][a] = real(0);
+        }
+        S.rho[p] = r;
+    }
+    // halo ring: density only
+    for (int j = tid; j < RING; j += NT) {
+        int lx, ly;
+        if (j < 2 * LX) {
+            ly = j / LX;
+            lx = j % LX;
+        } else if (j < 4 * LX) {
+            const int jj = j - 2 * LX;
+            ly = TY + 2 + jj / LX;
+            lx = jj % LX;
+        } else {
+            const int jj = j - 4 * LX;
+            ly = 2 + jj / 4;
+            const int c = jj % 4;
+            lx = c < 2 ? c : TX + c;
+        }
+        const int p = ly * LX + lx;
+        real r = real(0);
+        if (S.cls[p] == CLS_FLUID) {
+            const uint32_t n = S.row[ly] + S.col[lx];
+            r = io.ld(0, n);
+#pragma unroll
+            for (int a = 1; a < 9; ++a) r += io.ld(a, n);
+        }
+        S.rho[p] = r;
+    }
+    __syncthreads();
+
+    // psi on tile + 1 halo; wall nodes first get their virtual density
+    for (int i = tid; i < (TX + 2) * (TY + 2); i += NT) {
+        const int lx = 1 + i % (TX + 2), ly = 1 + i / (TX + 2);
+        const int p = ly * LX + lx;
+        const uint8_t c = S.cls[p];
+        real ps = real(0);
+        if (c == CLS_FLUID) {
+            ps = psi_of(C, S.rho[p], bad);
+        } else if (c == CLS_WALL) {
+            if (C.scheme == WET_IVD) {
+                // Eq. 17: w-weighted mean over the fluid neighbours
+                real num = real(0), den = real(0);
+                bool first = true;
+#pragma unroll
+                for (int a = 1; a < 9; ++a) {
+                    const int q = p + L::ex[a] + L::ey[a] * LX;
+                    if (S.cls[q] == CLS_FLUID) {
+                        const real w = real(L::w12[a]) * real(1.0 / 12.0);
+                        num = first ? w * S.rho[q] : num + w * S.rho[q];
+                        den = first ? w : den + w;
+                        first = false;
+                    }
+                }
+                const real rave = num / den;
+                const int kw = Fd.widx[S.row[ly] + S.col[lx]];
+                // Eq. 16 (phi scales, drho shifts) and the limiter
+                real rw = Fd.phi[kw] * rave - Fd.drho[kw];
+                rw = rw > C.rho_l ? C.rho_l : rw;
+                rw = rw < C.rho_g ? C.rho_g : rw;
+                S.rho[p] = rw;
+                ps = psi_of(C, rw, bad);
+            } else if (C.scheme == WET_VD) {
+                S.rho[p] = C.rho_w;
+                ps = C.psi_w;
+            } else {
+                S.rho[p] = real(0);
+            }
+        }
+        S.psi[p] = ps;
+    }
+    __syncthreads();
+}
+
+// Eq. 5 cohesive force and Eq. 8 adhesion at LDS position p; returns the
+// total force F (cohesion + adhesion + body force) and the cohesive part.
+template <typename real, int LX>
+__device__ __forceinline__ void d2q9_force(const Coef<real>& C, const uint8_t* cls, const real* psi,
+                                           int p, real rho, real* Fm, real* F) {
+    using L = D2Q9;
+    const real psi_c = psi[p];
+    real smx = real(0), smy = real(0), sax = real(0), say = real(0);
+#pragma unroll
+    for (int a = 1; a < 9; ++a) {
+        const int q = p + L::ex[a] + L::ey[a] * LX;
+        const real w = real(L::w12[a]) * real(1.0 / 12.0);
+        const real wp = w * psi[q];
+        if (L::ex[a] == 1) smx += wp;
+        if (L::ex[a] == -1) smx -= wp;
+        if (L::ey[a] == 1) smy += wp;
+        if (L::ey[a] == -1) smy -= wp;
+        if (C.scheme == WET_SFI && cls[q] != CLS_FLUID) {
+            if (L::ex[a] == 1) sax += w;
+            if (L::ex[a] == -1) sax -= w;
+            if (L::ey[a] == 1) say += w;
+            if (L::ey[a] == -1) say -= w;
+        }
+    }
+    Fm[0] = -C.G * psi_c * smx;
+    Fm[1] = -C.G * psi_c * smy;
+    const real fax = (C.scheme == WET_SFI) ? -C.G_w * rho * sax : real(0);
+    const real fay = (C.scheme == WET_SFI) ? -C.G_w * rho * say : real(0);
+    F[0] = Fm[0] + fax + C.body[0];
+    F[1] = Fm[1] + fay + C.body[1];
+}
+
+}  // namespace lbm

@@ -83,6 +83,10 @@ def lib():
             "lbm_get_variant": (C.c_int, [vp, C.POINTER(C.c_int32)]),
             "lbm_autotune": (C.c_int, [vp, i64, vp, C.POINTER(C.c_int32), dp]),
             "lbm_set_graph_steps": (C.c_int, [vp, i64]),
+            "lbm_adjoint_workspace_bytes": (C.c_size_t, [vp, i64]),
+            "lbm_step_ckpt": (C.c_int, [vp, i64, i64, vp]),
+            "lbm_adjoint": (C.c_int, [vp, C.c_int32, vp, i64, i64, vp, vp, C.c_size_t, vp, vp,
+                                      vp]),
             "lbm_batch_workspace_bytes": (C.c_size_t, [P, C.c_int32, C.POINTER(C.c_int32),
                                                        C.POINTER(C.c_int32), C.POINTER(i64)]),
             "lbm_create_batch": (C.c_int, [P, C.c_int32, C.POINTER(C.c_int32),
@@ -233,6 +237,20 @@ def lbm_autotune(ctx, steps, save=None, nvariants=None):
     ms = (C.c_double * nvariants)() if nvariants else None
     _check(lib().lbm_autotune(ctx, int(steps), _ptr(save), C.byref(best), ms), "lbm_autotune")
     return best.value, (list(ms) if ms is not None else None)
+
+
+def lbm_adjoint_workspace_bytes(ctx, K):
+    return lib().lbm_adjoint_workspace_bytes(ctx, int(K))
+
+
+def lbm_step_ckpt(ctx, T, K, ckpt):
+    _check(lib().lbm_step_ckpt(ctx, int(T), int(K), _ptr(ckpt)), "lbm_step_ckpt")
+
+
+def lbm_adjoint(ctx, seed_kind, seed, T, K, ckpt, work, grad_phi=None, grad_drho=None, lam0=None):
+    _check(lib().lbm_adjoint(ctx, int(seed_kind), _ptr(seed), int(T), int(K), _ptr(ckpt),
+                             _ptr(work), work.numel() * work.element_size(), _ptr(grad_phi),
+                             _ptr(grad_drho), _ptr(lam0)), "lbm_adjoint")
 
 
 def lbm_set_graph_steps(ctx, steps):
@@ -424,6 +442,54 @@ class Solver:
 
     def set_graph_steps(self, steps):
         lbm_set_graph_steps(self.ctx, steps)
+
+    # ---- checkpointed runs and the adjoint
+    def ckpt_buffer(self, T, K):
+        nseg = (int(T) + int(K) - 1) // int(K)
+        return torch.empty(nseg * self.Q * self.N, dtype=self.dtype, device=self.device)
+
+    def step_ckpt(self, T, K, ckpt):
+        lbm_step_ckpt(self.ctx, T, K, ckpt)
+
+    def adjoint(self, seed, T, K, ckpt, seed_kind=0, want_lam0=False):
+        """Gradients of a loss on the state at time T: seed is dL/drho(T)
+        (seed_kind 0) or dL/df(T) (seed_kind 1).  Returns (dL/dphi,
+        dL/ddrho[, dL/df(0)])."""
+        nw = len(self.wall_nodes())
+        work = torch.empty(lbm_adjoint_workspace_bytes(self.ctx, K), dtype=torch.uint8,
+                           device=self.device)
+        gp = torch.empty(max(nw, 1), dtype=self.dtype, device=self.device)
+        gd = torch.empty(max(nw, 1), dtype=self.dtype, device=self.device)
+        lam0 = torch.empty(self.Q * self.N, dtype=self.dtype, device=self.device) if want_lam0 else None
+        seed = torch.as_tensor(seed, dtype=self.dtype, device=self.device).contiguous().view(-1)
+        lbm_adjoint(self.ctx, seed_kind, seed, T, K, ckpt, work, gp, gd, lam0)
+        out = (gp[:nw], gd[:nw])
+        if want_lam0:
+            out = out + (lam0.view(self.Q, self.N),)
+        return out
+
+
+class LBMRollout(torch.autograd.Function):
+    """rho(T) of a D2Q9 lattice as a differentiable function of the
+    per-wall-node parameters (phi, drho) of the improved virtual-density
+    scheme.  Forward: T steps from the initial density rho0 with
+    checkpoints every K steps; backward: the hand-written discrete adjoint
+    (checkpointed recomputation), seeded with dL/drho(T) on fluid nodes."""
+
+    @staticmethod
+    def forward(ctx, phi, drho, solver, rho0, T, K):
+        solver.set_wetting(LBM_WET_IVD, 0.0, phi.detach().contiguous(), drho.detach().contiguous())
+        solver.set_fields(rho0)
+        ckpt = solver.ckpt_buffer(T, K)
+        solver.step_ckpt(T, K, ckpt)
+        rho_T = solver.get_fields(rho=True, u=False)["rho"]
+        ctx.solver, ctx.T, ctx.K, ctx.ckpt = solver, T, K, ckpt
+        return rho_T
+
+    @staticmethod
+    def backward(ctx, grad_rho):
+        gp, gd = ctx.solver.adjoint(grad_rho.contiguous(), ctx.T, ctx.K, ctx.ckpt)
+        return gp, gd, None, None, None, None
 
 
 class BatchSolver:

@@ -1,0 +1,239 @@
+"""The discrete adjoint of the D2Q9 step against derivatives the oracle and
+finite differences give.
+
+- one step, any state and any cotangent: <J v, w> = <v, J^T w>, with J v
+  from the oracle's complex-step tangent (exact to rounding) and J^T w from
+  the GPU adjoint;
+- whole rollouts on small lattices: dL/dphi_b and dL/ddrho_b against the
+  oracle's complex-step derivative of the same loss;
+- the 256 x 256 cylinder workload: FP64 central differences (h = 1e-6) on
+  16 seeded entries, 1e-5 relative; FP32 adjoint against FP64.
+"""
+import numpy as np
+import pytest
+
+from cases import Setup, lib_params
+from paper_1908_04443_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _solver(L, s, precision=8):
+    import torch
+    case = dict(s.case, precision=precision)
+    p = lib_params(L, s.op, case)
+    sol = L.Solver(p, max(len(s.walls), 1))
+    sol.set_geometry(s.solid)
+    return sol
+
+
+def _set_params(sol, s, phi, drho):
+    import torch
+    sch = {"ivd": 0, "vd": 1, "sfi": 2}[s.case.get("scheme", "ivd")]
+    if sch == 0:
+        sol.set_wetting(0, 0.0, torch.as_tensor(phi, dtype=sol.dtype, device="cuda"),
+                        torch.as_tensor(drho, dtype=sol.dtype, device="cuda"))
+    else:
+        sol.set_wetting(sch, s.case.get("rho_w", 0.0) if sch == 1 else s.case.get("G_w", 0.0))
+
+
+SMALL = dict(nx=24, ny=20, geometry=("disk", (12, 7), 4), init=("droplet", (12, 15), 4),
+             noise=1e-4, seed=11, sigma=0.105, precision=8)
+
+
+@pytest.mark.parametrize("scheme", ["ivd", "vd", "sfi"])
+def test_one_step_dot_product(oracle_mod, gpu_lib, scheme):
+    import torch
+    O = oracle_mod
+    s = Setup(O, dict(SMALL, scheme=scheme, rho_w=0.2, G_w=0.05))
+    rng = np.random.default_rng(3)
+    phi = 1.0 + 0.2 * rng.random(len(s.walls))
+    drho = 0.01 * rng.random(len(s.walls))
+    f0 = O.run(s.op, s.solid, s.f0, 25, phi, drho)  # a developed interface
+    fluid = (s.solid.ravel() == 0)
+    v = rng.normal(size=f0.shape) * fluid
+    w = rng.normal(size=f0.shape) * fluid
+    _, Jv = O.state_tangent_cs(s.op, s.solid, f0, v, 1, phi, drho)
+    lhs = float((Jv * w).sum())
+
+    sol = _solver(gpu_lib, s)
+    _set_params(sol, s, phi, drho)
+    sol.set_state(f0.ravel())
+    ckpt = sol.ckpt_buffer(1, 1)
+    sol.step_ckpt(1, 1, ckpt)
+    gp, gd, lam0 = sol.adjoint(w.ravel(), 1, 1, ckpt, seed_kind=1, want_lam0=True)
+    rhs = float((v * lam0.cpu().numpy()).sum())
+    print(f"<Jv,w> = {lhs:.15e}  <v,J^T w> = {rhs:.15e}")
+    assert abs(lhs - rhs) <= 1e-11 * max(abs(lhs), 1e-300)
+
+
+def _loss_and_seed(rho_T, target, fluid):
+    d = np.where(fluid, rho_T - target, 0.0)
+    return float((d * d).sum()), 2.0 * d
+
+
+@pytest.mark.parametrize("T,K", [(30, 7), (12, 12)])
+def test_parameter_gradients_vs_complex_step(oracle_mod, gpu_lib, T, K):
+    import torch
+    O = oracle_mod
+    case = dict(nx=16, ny=16, geometry=("disk", (8, 6), 3), init=("droplet", (8, 12), 3),
+                noise=1e-4, seed=5, sigma=0.105, precision=8, scheme="ivd")
+    s = Setup(O, case)
+    rng = np.random.default_rng(9)
+    nw = len(s.walls)
+    phi = 1.02 + 0.1 * rng.random(nw)
+    drho = 0.004 * rng.random(nw)
+    fluid = s.solid.ravel() == 0
+    target = np.where(fluid, s.rho0.ravel() * 0.97 + 0.002, 0.0)
+
+    sol = _solver(gpu_lib, s)
+    _set_params(sol, s, phi, drho)
+    sol.set_fields(s.rho0.ravel())
+    ckpt = sol.ckpt_buffer(T, K)
+    sol.step_ckpt(T, K, ckpt)
+    rho_T = sol.get_fields(rho=True, u=False)["rho"].cpu().numpy()
+    L_gpu, seed = _loss_and_seed(rho_T, target, fluid)
+    gp, gd = sol.adjoint(seed, T, K, ckpt)
+    gp, gd = gp.cpu().numpy(), gd.cpu().numpy()
+
+    cs_p = np.array([O.loss_grad_cs(s.op, s.solid, s.f0, T, target, 0, k, phi, drho)[1]
+                     for k in range(nw)])
+    cs_d = np.array([O.loss_grad_cs(s.op, s.solid, s.f0, T, target, 1, k, phi, drho)[1]
+                     for k in range(nw)])
+    L_or = O.loss(s.op, s.solid, s.f0, T, target, phi, drho)
+    assert abs(L_gpu - L_or) <= 1e-12 * L_or
+    ep = np.abs(gp - cs_p).max() / np.abs(cs_p).max()
+    ed = np.abs(gd - cs_d).max() / np.abs(cs_d).max()
+    print(f"phi grad rel err {ep:.2e}, drho grad rel err {ed:.2e}, |g| {np.abs(cs_p).max():.3e}")
+    assert ep <= 1e-9 and ed <= 1e-9
+
+
+def _c4(O, n=256, R=40, r0=32, T=1000):
+    from paper_1908_04443_amd import workloads as W
+    op = O.make_params(nx=n, ny=n, sigma=0.105)
+    d = W.c4_adjoint(op.rho_g, op.rho_l, n=n, R=R, r0=r0)
+    return op, d
+
+
+def _run_loss(L, sol, phi, drho, rho0, T, target, fluid):
+    import torch
+    sol.set_wetting(0, 0.0, torch.as_tensor(phi, dtype=sol.dtype, device="cuda"),
+                    torch.as_tensor(drho, dtype=sol.dtype, device="cuda"))
+    sol.set_fields(rho0)
+    sol.step(T)
+    rho = sol.get_fields(rho=True, u=False)["rho"].double().cpu().numpy()
+    d = np.where(fluid, rho - target, 0.0)
+    return float((d * d).sum()), rho
+
+
+def test_c4_adjoint_vs_central_differences(oracle_mod, gpu_lib):
+    """256 x 256, cylinder R = 40, droplet r = 32 tangent on top; target from
+    the forward model at a seeded smooth 40-140 deg angle profile; loss
+    L = sum_fluid (rho_T - rho_target)^2.  The limiter makes L only
+    piecewise smooth: at phi = 1, drho = 0 the wall densities sit at rho_g or
+    rho_l, where +-h flips clamps.  The check therefore runs at phi = 1,
+    drho = 0.003 (liquid-side walls well inside the bounds, gas-side walls
+    well below rho_g), and skips an entry whose one-sided differences
+    disagree (a clamp switch inside +-h)."""
+    from paper_1908_04443_amd import workloads as W
+    O = oracle_mod
+    n, T, K = 256, 1000, 50
+    op, d = _c4(O, n=n, T=T)
+    p = lib_params(gpu_lib, op, dict(precision=8))
+    sol = gpu_lib.Solver(p, int(d["solid"].sum()))
+    sol.set_geometry(d["solid"])
+    walls = sol.wall_nodes()
+    fluid = d["solid"].ravel() == 0
+    tphi, tdrho = W.c4_target_params(d["solid"], n)
+    _, target = _run_loss(gpu_lib, sol, tphi.ravel()[walls], tdrho.ravel()[walls],
+                          d["rho"].ravel(), T, np.zeros(n * n), fluid)
+    phi0, drho0 = np.ones(len(walls)), np.full(len(walls), 0.003)
+    import torch
+    sol.set_wetting(0, 0.0, torch.as_tensor(phi0, dtype=sol.dtype, device="cuda"),
+                    torch.as_tensor(drho0, dtype=sol.dtype, device="cuda"))
+    sol.set_fields(d["rho"].ravel())
+    ckpt = sol.ckpt_buffer(T, K)
+    sol.step_ckpt(T, K, ckpt)
+    rho_T = sol.get_fields(rho=True, u=False)["rho"].cpu().numpy()
+    seed = 2.0 * np.where(fluid, rho_T - target, 0.0)
+    gp, gd = (g.cpu().numpy() for g in sol.adjoint(seed, T, K, ckpt))
+    L0, _ = _run_loss(gpu_lib, sol, phi0, drho0, d["rho"].ravel(), T, target, fluid)
+    rng = np.random.default_rng(4)
+    live = np.flatnonzero((np.abs(gp) + np.abs(gd)) > 0)  # walls not held by the limiter
+    assert len(live) >= 16
+    picks = rng.choice(live, 16, replace=False)
+    checked = 0
+    h = 1e-6
+    for k in picks:
+        for which, g in ((0, gp), (1, gd)):
+            pp, pm = phi0.copy(), phi0.copy()
+            dp, dm = drho0.copy(), drho0.copy()
+            if which == 0:
+                pp[k] += h
+                pm[k] -= h
+            else:
+                dp[k] += h
+                dm[k] -= h
+            lp, _ = _run_loss(gpu_lib, sol, pp, dp, d["rho"].ravel(), T, target, fluid)
+            lm, _ = _run_loss(gpu_lib, sol, pm, dm, d["rho"].ravel(), T, target, fluid)
+            fd = (lp - lm) / (2 * h)
+            fwd, bwd = (lp - L0) / h, (L0 - lm) / h
+            scale = max(abs(fd), 1e-2 * np.abs(g).max())
+            if abs(fwd - bwd) > 2e-5 * scale:
+                print(f"wall {k}: one-sided slopes differ ({fwd:.6e} vs {bwd:.6e}), skipped")
+                continue
+            checked += 1
+            print(f"wall {k} {'phi' if which == 0 else 'drho'}: adj {g[k]:.10e} fd {fd:.10e}")
+            assert abs(g[k] - fd) <= 1e-5 * scale
+    assert checked >= 20
+
+
+def test_fp32_adjoint_tracks_fp64(oracle_mod, gpu_lib):
+    from paper_1908_04443_amd import workloads as W
+    import torch
+    O = oracle_mod
+    n, T, K = 256, 300, 50
+    op, d = _c4(O, n=n)
+    grads = {}
+    for prec in (8, 4):
+        p = lib_params(gpu_lib, op, dict(precision=prec))
+        sol = gpu_lib.Solver(p, int(d["solid"].sum()))
+        sol.set_geometry(d["solid"])
+        walls = sol.wall_nodes()
+        fluid = d["solid"].ravel() == 0
+        tphi, tdrho = W.c4_target_params(d["solid"], n)
+        _, target = _run_loss(gpu_lib, sol, tphi.ravel()[walls], tdrho.ravel()[walls],
+                              d["rho"].ravel(), T, np.zeros(n * n), fluid)
+        sol.set_wetting(0, 0.0, phi0=1.0, drho0=0.0)
+        sol.set_fields(d["rho"].ravel())
+        ckpt = sol.ckpt_buffer(T, K)
+        sol.step_ckpt(T, K, ckpt)
+        rho_T = sol.get_fields(rho=True, u=False)["rho"].double().cpu().numpy()
+        seed = 2.0 * np.where(fluid, rho_T - target, 0.0)
+        grads[prec] = np.concatenate([g.double().cpu().numpy() for g in sol.adjoint(seed, T, K, ckpt)])
+    a, b = grads[8], grads[4]
+    cos = float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b)))
+    big = np.abs(a) > 0.1 * np.abs(a).max()
+    rel = np.abs(a - b)[big] / np.abs(a)[big]
+    print(f"cosine {cos:.6f}, max rel on large entries {rel.max():.2e}")
+    assert cos >= 0.999 and rel.max() <= 1e-2
+
+
+def test_autograd_function_matches_direct_adjoint(oracle_mod, gpu_lib):
+    import torch
+    O = oracle_mod
+    s = Setup(O, dict(SMALL, scheme="ivd"))
+    sol = _solver(gpu_lib, s)
+    nw = len(s.walls)
+    phi = torch.full((nw,), 1.05, dtype=torch.float64, device="cuda", requires_grad=True)
+    drho = torch.full((nw,), 0.001, dtype=torch.float64, device="cuda", requires_grad=True)
+    rho0 = torch.as_tensor(s.rho0.ravel(), device="cuda")
+    fluid = torch.as_tensor(s.solid.ravel() == 0, device="cuda")
+    target = torch.where(fluid, rho0 * 0.99, torch.zeros_like(rho0))
+    rho_T = gpu_lib.LBMRollout.apply(phi, drho, sol, rho0, 20, 6)
+    loss = (torch.where(fluid, rho_T - target, torch.zeros_like(rho_T)) ** 2).sum()
+    loss.backward()
+    cs = np.array([O.loss_grad_cs(s.op, s.solid, s.f0, 20, target.cpu().numpy(), 0, k,
+                                  np.full(nw, 1.05), np.full(nw, 0.001))[1] for k in range(nw)])
+    g = phi.grad.cpu().numpy()
+    assert np.abs(g - cs).max() <= 1e-9 * np.abs(cs).max()
