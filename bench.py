@@ -33,7 +33,7 @@ def log(*a):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("lbm_device.hpp", "step2d.hip", "step_march.hip"):
+    for f in ("lbm_device.hpp", "lbm_kernels.hpp", "tile2d.hpp", "step2d.hip", "step_march.hip"):
         with open(os.path.join(ROOT, "paper_1908_04443_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -231,6 +231,19 @@ def cpu_baseline(data, lbm_params, steps):
                        f"oracle steps ({dt:.1f} s)")
 
 
+def copy_calibration(nbytes, reps):
+    """A plain device-to-device copy of known size, the reference point that
+    converts the HBM counters of the profiler into bytes."""
+    import torch
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -241,6 +254,11 @@ def main():
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--c2-steps", type=int, default=500)
     ap.add_argument("--c3-steps", type=int, default=500)
+    ap.add_argument("--secondary", default="c2,c3,c4",
+                    help="secondary workloads to run: any of c2 (D3Q19 256^3), c3 (96 cases), "
+                         "c4 (adjoint)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device to device 5 times (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -249,6 +267,9 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration << 20, 5)
+        return
     from paper_1908_04443_amd import lbm as L
     from paper_1908_04443_amd import workloads as W
     if not os.path.exists(L.LIB_PATH):
@@ -296,25 +317,27 @@ def main():
                   "rho_min_max": c1["rho"]},
     }
 
-    if not args.no_secondary:
+    want = set() if args.no_secondary else set(x for x in args.secondary.split(",") if x)
+    out["secondary"] = {}
+    if "c2" in want:
         log(f"C2: D3Q19 256^3 FP32 sphere, {args.c2_steps} steps")
         c2 = run_c2(L, W, args.c2_steps, 20)
         k2 = c2["ms_events"] / 1e3 / args.c2_steps
         b2 = 2 * 19 * 4 * c2["n_fluid"]
-        out["secondary"] = {
-            "d3q19_256cubed_fp32": {
-                "mlups": round(c2["N"] * args.c2_steps / c2["wall"] / 1e6, 2),
-                "achieved_GBs": round(b2 / k2 / 1e9, 1),
-                "frac": round(b2 / k2 / 1e9 / HBM_PEAK_GBS, 4),
-                "kernel_ms": round(k2 * 1e3, 5), "steps": args.c2_steps,
-                "traffic": measured_traffic("k_step_march", "c2")},
-        }
+        out["secondary"]["d3q19_256cubed_fp32"] = {
+            "mlups": round(c2["N"] * args.c2_steps / c2["wall"] / 1e6, 2),
+            "achieved_GBs": round(b2 / k2 / 1e9, 1),
+            "frac": round(b2 / k2 / 1e9 / HBM_PEAK_GBS, 4),
+            "kernel_ms": round(k2 * 1e3, 5), "steps": args.c2_steps,
+            "traffic": measured_traffic("k_step_march", "c2")}
         log(f"C2: {out['secondary']['d3q19_256cubed_fp32']}")
+    if "c3" in want:
         log(f"C3: 96 uneven D2Q9 FP32 cases, {args.c3_steps} steps, batched vs one per launch")
         c3 = run_c3(L, W, args.c3_steps, 20)
         out["secondary"]["batched_96_cases_fp32"] = {k: (round(v, 3) if isinstance(v, float) else v)
                                                      for k, v in c3.items()}
         log(f"C3: {out['secondary']['batched_96_cases_fp32']}")
+    if "c4" in want:
         log("C4: adjoint of the 256^2 D2Q9 FP32 workload, T = 1000, K = 50")
         out["secondary"]["adjoint_256_fp32"] = run_c4(L, W)
         log(f"C4: {out['secondary']['adjoint_256_fp32']}")
