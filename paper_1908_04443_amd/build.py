@@ -4,8 +4,9 @@ Every source under csrc/ is compiled by hipcc for gfx950 (device code) and
 the host objects are linked with g++ against the HIP runtime that PyTorch
 ships, so that one process holds a single HIP runtime when the library is
 used next to torch.  Packed-FP32 code generation is disabled (see the
-compile flags), FMA contraction is off so that the FP64 build follows the
-same rounding steps as a plain scalar evaluation.
+compile flags).  The kernel sources are compiled once per precision: the
+FP64 objects without FMA contraction, so that they follow the rounding steps
+of a plain scalar evaluation, the FP32 objects with contraction.
 """
 import os
 import subprocess
@@ -19,6 +20,8 @@ BUILD = os.path.join(HERE, "_build")
 
 SOURCES = ["api.cpp", "thermo.cpp", "geometry.cpp", "step2d.hip", "step_march.hip",
            "aux.hip", "adjoint2d.hip"]
+# kernels compiled once per precision: FP32 with FMA contraction, FP64 without
+SPLIT = {"step2d.hip", "step_march.hip", "adjoint2d.hip"}
 EXTRA_SOURCES = []
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -49,13 +52,25 @@ def _run(cmd, verbose):
 def build(verbose=False, jobs=8):
     os.makedirs(BUILD, exist_ok=True)
     objs, procs = [], []
+    jobs_list = []
     for src in SOURCES + EXTRA_SOURCES:
         path = os.path.join(CSRC, src)
-        obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-        if src.endswith(".hip"):
-            cmd = [HIPCC, *COMMON, *DEVICE, "-x", "hip", "-c", path, "-o", obj]
+        stem = os.path.splitext(src)[0]
+        if src in SPLIT:
+            for prec, contract in ((4, "fast"), (8, "off")):
+                flags = [f if f != "-ffp-contract=off" else f"-ffp-contract={contract}"
+                         for f in COMMON]
+                obj = os.path.join(BUILD, f"{stem}_f{8 * prec}.o")
+                jobs_list.append(([HIPCC, *flags, *DEVICE, f"-DLBM_PREC={prec}", "-x", "hip",
+                                   "-c", path, "-o", obj], obj, src))
+        elif src.endswith(".hip"):
+            obj = os.path.join(BUILD, stem + ".o")
+            jobs_list.append(([HIPCC, *COMMON, *DEVICE, "-x", "hip", "-c", path, "-o", obj],
+                              obj, src))
         else:
-            cmd = [HIPCC, *COMMON, "-c", path, "-o", obj]
+            obj = os.path.join(BUILD, stem + ".o")
+            jobs_list.append(([HIPCC, *COMMON, "-c", path, "-o", obj], obj, src))
+    for cmd, obj, src in jobs_list:
         objs.append(obj)
         if verbose:
             print(" ".join(cmd), flush=True)

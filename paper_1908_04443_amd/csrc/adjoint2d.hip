@@ -25,6 +25,13 @@
 //    neighbour x = b + e_a gets w_a phi_b dL/dr / sum_fluid(w) (Eq. 17);
 //    fluid y: ext(y) = dpsi/drho(y) * gathered dL/dpsi(y) + wall terms.
 // lam(t) = partial + ext (ext broadcast to all directions).
+// Built twice: LBM_PREC == 4 holds the FP32 instantiations (compiled with
+// FMA contraction), LBM_PREC == 8 the FP64 ones (no contraction, so that
+// FP64 follows the rounding steps of a plain scalar evaluation).  Without
+// LBM_PREC both are instantiated.
+#ifndef LBM_PREC
+#define LBM_PREC 0
+#endif
 #include "tile2d.hpp"
 
 namespace lbm {
@@ -302,17 +309,29 @@ hipError_t launch_adj_finish(const uint8_t* cls, const real* lam, const real* ex
     return hipGetLastError();
 }
 
+#if LBM_PREC != 8
 template hipError_t launch_adjoint2d<float>(const Coef<float>&, const Fields<float>&,
                                             const AdjArgs<float>&, hipStream_t);
+#endif
+#if LBM_PREC != 4
 template hipError_t launch_adjoint2d<double>(const Coef<double>&, const Fields<double>&,
                                              const AdjArgs<double>&, hipStream_t);
+#endif
+#if LBM_PREC != 8
 template hipError_t launch_adj_seed<float>(int, const uint8_t*, const float*, float*, float*,
                                            uint32_t, hipStream_t);
+#endif
+#if LBM_PREC != 4
 template hipError_t launch_adj_seed<double>(int, const uint8_t*, const double*, double*, double*,
                                             uint32_t, hipStream_t);
+#endif
+#if LBM_PREC != 8
 template hipError_t launch_adj_finish<float>(const uint8_t*, const float*, const float*, float*,
                                              uint32_t, hipStream_t);
+#endif
+#if LBM_PREC != 4
 template hipError_t launch_adj_finish<double>(const uint8_t*, const double*, const double*, double*,
                                               uint32_t, hipStream_t);
+#endif
 
 }  // namespace lbm

@@ -187,12 +187,29 @@ struct PopIO {
         if constexpr (BUF) buf_st<real>(v, rout, n * (uint32_t)sizeof(real), (uint32_t)a * N * (uint32_t)sizeof(real));
         else fout[(size_t)a * N + n] = v;
     }
+    // store to node n + delta of direction a, delta uniform across the
+    // wavefront: the shift goes into the scalar offset, so every direction
+    // shares the per-lane offset of n.  Needs a * N + delta >= 0.
+    __device__ __forceinline__ void st_shift(int a, int delta, uint32_t n, real v) const {
+        if constexpr (BUF)
+            buf_st<real>(v, rout, n * (uint32_t)sizeof(real),
+                         (uint32_t)((int)(a * N) + delta) * (uint32_t)sizeof(real));
+        else fout[(int64_t)a * N + n + delta] = v;
+    }
 };
 
 __device__ __forceinline__ int wrapi(int v, int n) {
     // any integer into [0, n); tiles may cover the lattice several times
     v %= n;
     return v < 0 ? v + n : v;
+}
+
+// a / b: IEEE division in FP64; in FP32 a times the hardware reciprocal
+// (v_rcp_f32, 1 ulp), which is well inside the FP32 error budget of a step.
+template <typename real>
+__device__ __forceinline__ real fdiv(real a, real b) {
+    if constexpr (sizeof(real) == 4) return a * __builtin_amdgcn_rcpf(b);
+    else return a / b;
 }
 
 // ---------------------------------------------------- equation of state
@@ -202,11 +219,11 @@ __device__ __forceinline__ real eos_p(const Coef<real>& C, real rho) {
         real h = C.eos_b * real(0.25) * rho;
         real om = real(1) - h;
         real num = real(1) + h + h * h - h * h * h;
-        return rho * C.eos_RT * num / (om * om * om) - C.eos_a * rho * rho;
+        return fdiv(rho * C.eos_RT * num, om * om * om) - C.eos_a * rho * rho;
     } else {
         real br = C.eos_b * rho;
-        return rho * C.eos_RT / (real(1) - br) -
-               C.eos_aphi * rho * rho / (real(1) + real(2) * br - br * br);
+        return fdiv(rho * C.eos_RT, real(1) - br) -
+               fdiv(C.eos_aphi * rho * rho, real(1) + real(2) * br - br * br);
     }
 }
 
@@ -291,6 +308,74 @@ __device__ __forceinline__ real src_row(const Coef<real>& C, int k, const real* 
     }
 }
 
+// FP32 D2Q9 collision.  Same m = M f, relaxation and M^-1 as the row-by-row
+// form below, with two changes that matter in single precision:
+//  * the Lallemand-Luo rows are factored into shared partial sums (axis
+//    pairs, diagonal pairs), about a third of the arithmetic;
+//  * the result is formed as an increment, f* = f + M^-1 (m* - m).  The
+//    increment vanishes at equilibrium and its entries sum to zero up to
+//    rounding of the (small) increment, so a resting bulk region does not
+//    re-round its populations every step.  Re-forming f* from m* instead
+//    repeats the same rounding error at every node of a uniform region each
+//    step, which shows up as a steady FP32 mass drift.
+// One reciprocal of rho serves both velocity components.
+__device__ __forceinline__ void collide_d2q9_f32(const Coef<float>& C, const float* f, float rho,
+                                                 const float* F, const float* Fm, float psi,
+                                                 float* fs, float* u_out) {
+    const float A = f[1] + f[3], B = f[2] + f[4];
+    const float p57 = f[5] + f[7], p68 = f[6] + f[8];
+    const float d13 = f[1] - f[3], d24 = f[2] - f[4];
+    const float u57 = f[5] - f[7], v68 = f[6] - f[8];
+    const float AB = A + B, Dg = p57 + p68;
+    const float Ex = u57 - v68, Ey = u57 + v68;
+    const float m_e = 2.0f * Dg - AB - 4.0f * f[0];
+    const float m_eps = Dg - 2.0f * AB + 4.0f * f[0];
+    const float jx = d13 + Ex, jy = d24 + Ey;
+    const float m_qx = Ex - 2.0f * d13, m_qy = Ey - 2.0f * d24;
+    const float m_pxx = A - B, m_pxy = p57 - p68;
+
+    const float inv = __builtin_amdgcn_rcpf(rho);
+    const float ux = (jx + 0.5f * F[0]) * inv, uy = (jy + 0.5f * F[1]) * inv;
+    u_out[0] = ux;
+    u_out[1] = uy;
+    const float uF = ux * F[0] + uy * F[1];
+    const float u2 = ux * ux + uy * uy;
+    const float fm2 = Fm[0] * Fm[0] + Fm[1] * Fm[1];
+    const float sgm = (psi > 0.0f) ? fdiv(fm2, psi * psi) : 0.0f;
+
+    const float se = C.s[GRP_E], sp = C.s[GRP_EPS], sq = C.s[GRP_Q], sn = C.s[GRP_NU];
+    // m* - m = s (m_eq - m) + (1 - s/2) Src per row (Eq. 2, Eq. 7); the
+    // density row does not change and the momentum rows change by F
+    const float de = se * (rho * (3.0f * u2 - 2.0f) - m_e) +
+                     (1.0f - 0.5f * se) * (6.0f * uF + C.sig_e * sgm);
+    const float dp = sp * (rho * (1.0f - 3.0f * u2) - m_eps) -
+                     (1.0f - 0.5f * sp) * (6.0f * uF + C.sig_eps * sgm);
+    const float dqx = -sq * (rho * ux + m_qx) - (1.0f - 0.5f * sq) * F[0];
+    const float dqy = -sq * (rho * uy + m_qy) - (1.0f - 0.5f * sq) * F[1];
+    const float dxx = sn * (rho * (ux * ux - uy * uy) - m_pxx) +
+                      (1.0f - 0.5f * sn) * 2.0f * (ux * F[0] - uy * F[1]);
+    const float dxy = sn * (rho * ux * uy - m_pxy) + (1.0f - 0.5f * sn) * (ux * F[1] + uy * F[0]);
+
+    // f* - f = M^T diag(1/norm) (m* - m)
+    const float e1 = de * (1.0f / 36.0f), p1 = dp * (1.0f / 36.0f);
+    const float jx1 = F[0] * (1.0f / 6.0f), jy1 = F[1] * (1.0f / 6.0f);
+    const float qx1 = dqx * (1.0f / 12.0f), qy1 = dqy * (1.0f / 12.0f);
+    const float xx1 = dxx * 0.25f, xy1 = dxy * 0.25f;
+    fs[0] = f[0] + (4.0f * (p1 - e1));
+    const float ca = -e1 - 2.0f * p1;
+    const float X = jx1 - 2.0f * qx1, Y = jy1 - 2.0f * qy1;
+    fs[1] = f[1] + ((ca + xx1) + X);
+    fs[3] = f[3] + ((ca + xx1) - X);
+    fs[2] = f[2] + ((ca - xx1) + Y);
+    fs[4] = f[4] + ((ca - xx1) - Y);
+    const float cd = 2.0f * e1 + p1;
+    const float Px = jx1 + qx1, Py = jy1 + qy1;
+    fs[5] = f[5] + ((cd + xy1) + (Px + Py));
+    fs[7] = f[7] + ((cd + xy1) - (Px + Py));
+    fs[6] = f[6] + ((cd - xy1) + (Py - Px));
+    fs[8] = f[8] + ((cd - xy1) - (Py - Px));
+}
+
 // Post-collision populations of one fluid node (Eq. 2, forcing of Eq. 7):
 // m = M f, m* = m - S (m - m_eq) + (I - S/2) Src, f* = M^-1 m*.
 // in: f (populations), rho, F (total force), Fm (cohesive force of Eq. 5),
@@ -300,6 +385,10 @@ template <typename L, typename real>
 __device__ __forceinline__ void collide(const Coef<real>& C, const real* f, real rho,
                                         const real* F, const real* Fm, real psi,
                                         real* fs, real* u_out) {
+    if constexpr (L::Q == 9 && sizeof(real) == 4) {
+        collide_d2q9_f32(C, f, rho, F, Fm, psi, fs, u_out);
+        return;
+    }
     constexpr int Q = L::Q;
     real m[Q];
 #pragma unroll
@@ -333,18 +422,23 @@ __device__ __forceinline__ void collide(const Coef<real>& C, const real* f, real
     // Conserved rows: density keeps its value (S_0 = 0, m_eq = rho) and the
     // momentum rows give j + F for any relaxation rate, since
     // j - j_eq = -F/2.  All other rows relax with their group's rate.
+    // FP32 forms the increment f* - f = M^-1 (m* - m) (it vanishes at
+    // equilibrium, so a resting region does not re-round its populations
+    // every step); FP64 forms f* = M^-1 m* in the order of Eq. 2.
+    constexpr bool INC = sizeof(real) == 4;
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
         real mk;
-        if (k == 0) mk = m[0];
-        else if (k == 3) mk = m[3] + Fv[0];
-        else if (k == 5) mk = m[5] + Fv[1];
-        else if (L::D == 3 && k == 7) mk = m[7] + Fv[2];
+        if (k == 0) mk = INC ? real(0) : m[0];
+        else if (k == 3) mk = INC ? Fv[0] : m[3] + Fv[0];
+        else if (k == 5) mk = INC ? Fv[1] : m[5] + Fv[1];
+        else if (L::D == 3 && k == 7) mk = INC ? Fv[2] : m[7] + Fv[2];
         else {
             const real sk = C.s[L::grp[k]];
             const real me = meq_row<L, real>(k, rho, u, u2);
             const real sr = src_row<L, real>(C, k, u, Fv, uF, sgm);
-            mk = m[k] - sk * (m[k] - me) + (real(1) - real(0.5) * sk) * sr;
+            mk = INC ? sk * (me - m[k]) + (real(1) - real(0.5) * sk) * sr
+                     : m[k] - sk * (m[k] - me) + (real(1) - real(0.5) * sk) * sr;
         }
         m[k] = mk * real(1.0 / L::norm[k]);
     }
@@ -355,11 +449,12 @@ __device__ __forceinline__ void collide(const Coef<real>& C, const real* f, real
 #pragma unroll
         for (int k = 0; k < Q; ++k) {
             if (L::M[k][a] == 0) continue;
+            if (INC && k == 0) continue;  // the density row does not change
             real term = (L::M[k][a] == 1) ? m[k] : (L::M[k][a] == -1) ? -m[k] : real(L::M[k][a]) * m[k];
             s = first ? term : s + term;
             first = false;
         }
-        fs[a] = s;
+        fs[a] = INC ? f[a] + s : s;
     }
 }
 

@@ -19,6 +19,16 @@
 // State: post-streaming populations, SoA f[a*N + n]; fin -> fout ping-pong.
 // Only fluid slots of fout are written; a population that would enter a
 // solid node is written back to its origin in the opposite direction.
+// Built twice: LBM_PREC == 4 holds the FP32 instantiations (compiled with
+// FMA contraction), LBM_PREC == 8 the FP64 ones (no contraction, so that
+// FP64 follows the rounding steps of a plain scalar evaluation).  Without
+// LBM_PREC both are instantiated.
+#ifndef LBM_PREC
+#define LBM_PREC 0
+#endif
+#include <array>
+#include <utility>
+
 #include "tile2d.hpp"
 
 namespace lbm {
@@ -45,6 +55,8 @@ __device__ __forceinline__ void d2q9_tile(const Coef<real>& C, const Fields<real
     double d_sum = 0.0;
     real d_umax = real(0), d_rmin = real(1e30), d_rmax = real(-1e30);
     int d_cnt = 0;
+    // the tile and its 1-node ring lie inside the lattice without wrapping
+    const bool interior = x0 >= 1 && y0 >= 1 && x0 + TX + 1 <= nx && y0 + TY + 1 <= ny;
 
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
@@ -91,14 +103,24 @@ __device__ __forceinline__ void d2q9_tile(const Coef<real>& C, const Fields<real
         real fs[9], u[2];
         collide<L, real>(C, f[k], rho, F, Fm, psi_c, fs, u);
         // push streaming with halfway bounce-back
+        if (interior) {
+            // no neighbour wraps: the target is n + ex + ey nx
 #pragma unroll
-        for (int a = 0; a < 9; ++a) {
-            const int q = p + L::ex[a] + L::ey[a] * LX;
-            if (S.cls[q] == CLS_FLUID) {
-                const uint32_t m = S.row[ly + 2 + L::ey[a]] + S.col[tx + 2 + L::ex[a]];
-                io.st(a, m, fs[a]);
-            } else {
-                io.st(L::opp[a], n, fs[a]);
+            for (int a = 0; a < 9; ++a) {
+                const int q = p + L::ex[a] + L::ey[a] * LX;
+                if (S.cls[q] == CLS_FLUID) io.st_shift(a, L::ex[a] + L::ey[a] * nx, n, fs[a]);
+                else io.st(L::opp[a], n, fs[a]);
+            }
+        } else {
+#pragma unroll
+            for (int a = 0; a < 9; ++a) {
+                const int q = p + L::ex[a] + L::ey[a] * LX;
+                if (S.cls[q] == CLS_FLUID) {
+                    const uint32_t m = S.row[ly + 2 + L::ey[a]] + S.col[tx + 2 + L::ex[a]];
+                    io.st(a, m, fs[a]);
+                } else {
+                    io.st(L::opp[a], n, fs[a]);
+                }
             }
         }
     }
@@ -109,14 +131,27 @@ __device__ __forceinline__ void d2q9_tile(const Coef<real>& C, const Fields<real
     if (bad) Fd.flag[0] = 1;
 }
 
-template <typename real, int TX, int TY, int NT, int MODE, bool XCD, bool BUF>
-__global__ __launch_bounds__(NT) void k_step_d2q9(Coef<real> C, Fields<real> Fd,
-                                                  FieldOut<real> Out) {
-    const int gxb = gridDim.x, nblk = gridDim.x * gridDim.y;
+// Workgroup -> tile order.  XCD: consecutive tiles go to one XCD (each XCD
+// gets a contiguous range of the order, so neighbouring tiles share an L2).
+// ORD > 0: the order runs through column groups ORD tiles wide, row by row
+// inside a group, so the tile above a tile is only ORD places earlier.
+template <typename real, int TX, int TY, int NT, int MODE, bool XCD, bool BUF, int ORD, int OCC>
+__global__ __launch_bounds__(NT, OCC) void k_step_d2q9(Coef<real> C, Fields<real> Fd,
+                                                       FieldOut<real> Out) {
+    const int gxb = gridDim.x, gyb = gridDim.y, nblk = gxb * gyb;
     int bid = blockIdx.x + gxb * blockIdx.y;
     if (XCD) bid = remap_xcd(bid, nblk);
-    d2q9_tile<real, TX, TY, NT, MODE, BUF>(C, Fd, Out, C.nx, C.ny, (bid % gxb) * TX,
-                                           (bid / gxb) * TY, bid);
+    int bx, by;
+    if (ORD > 0) {
+        const int g = bid / (ORD * gyb), r = bid - g * (ORD * gyb);
+        const int w = (gxb - g * ORD) < ORD ? (gxb - g * ORD) : ORD;
+        bx = g * ORD + r % w;
+        by = r / w;
+    } else {
+        bx = bid % gxb;
+        by = bid / gxb;
+    }
+    d2q9_tile<real, TX, TY, NT, MODE, BUF>(C, Fd, Out, C.nx, C.ny, bx * TX, by * TY, bid);
 }
 
 // Many independent lattices in one launch: workgroup -> (case, tile) through
@@ -145,22 +180,28 @@ __global__ __launch_bounds__(NT) void k_step_d2q9_batch(Coef<real> C, BatchArgs<
 struct Shape2D {
     int TX, TY, NT;
     bool xcd;
+    int ord;  // column-group width of the tile order (0: row-major)
+    int occ;  // minimum waves per SIMD asked of the register allocator
 };
 
 template <typename real>
 struct Variants2D;
 template <>
 struct Variants2D<float> {
-    static constexpr int count = 6;
-    static constexpr Shape2D shape[count] = {{64, 16, 256, true},  {64, 16, 256, false},
-                                             {128, 8, 256, true},  {64, 32, 256, true},
-                                             {256, 4, 256, true},  {128, 16, 256, true}};
+    static constexpr int count = 12;
+    static constexpr Shape2D shape[count] = {
+        {64, 16, 256, true, 0, 1},  {64, 16, 256, false, 0, 1}, {128, 8, 256, true, 0, 1},
+        {64, 32, 256, true, 0, 1},  {256, 4, 256, true, 0, 1},  {128, 16, 256, true, 0, 1},
+        {64, 16, 256, true, 8, 1},  {128, 8, 256, true, 4, 1},  {64, 16, 256, true, 0, 8},
+        {256, 8, 512, true, 0, 1},  {128, 16, 512, true, 0, 1}, {64, 32, 256, true, 8, 1}};
 };
 template <>
 struct Variants2D<double> {
-    static constexpr int count = 3;
-    static constexpr Shape2D shape[count] = {{64, 8, 256, true}, {64, 8, 256, false},
-                                             {128, 4, 256, true}};
+    static constexpr int count = 4;
+    static constexpr Shape2D shape[count] = {{64, 8, 256, true, 0, 1},
+                                             {64, 8, 256, false, 0, 1},
+                                             {128, 4, 256, true, 0, 1},
+                                             {64, 8, 256, true, 8, 1}};
 };
 
 // variants beyond the tile shapes are the y-sweep kernel (step_march.hip)
@@ -180,21 +221,21 @@ static void launch_v(const Coef<real>& C, const Fields<real>& F, const FieldOut<
                      hipStream_t s) {
     constexpr Shape2D sh = Variants2D<real>::shape[V];
     dim3 grid((C.nx + sh.TX - 1) / sh.TX, (C.ny + sh.TY - 1) / sh.TY);
-    hipLaunchKernelGGL((k_step_d2q9<real, sh.TX, sh.TY, sh.NT, MODE, sh.xcd, BUF>), grid,
-                       dim3(sh.NT), 0, s, C, F, O);
+    hipLaunchKernelGGL((k_step_d2q9<real, sh.TX, sh.TY, sh.NT, MODE, sh.xcd, BUF, sh.ord, sh.occ>),
+                       grid, dim3(sh.NT), 0, s, C, F, O);
+}
+
+template <typename real, int MODE, bool BUF, size_t... I>
+static auto table_v(std::index_sequence<I...>) {
+    using Fn = void (*)(const Coef<real>&, const Fields<real>&, const FieldOut<real>&,
+                        hipStream_t);
+    return std::array<Fn, sizeof...(I)>{&launch_v<real, (int)I, MODE, BUF>...};
 }
 
 // population arrays of 4 GiB or more cannot use 32-bit buffer offsets
 template <typename real>
 static bool fits_buffer(const Coef<real>& C, int Q) {
     return (uint64_t)Q * (uint64_t)C.nx * C.ny * C.nz * sizeof(real) <= 0xFFFFFFFFull;
-}
-
-template <typename real, int V>
-static void launch_mode(const Coef<real>& C, const Fields<real>& F, const FieldOut<real>& O,
-                        int mode, hipStream_t s) {
-    if (mode == MODE_STEP) launch_v<real, V, MODE_STEP>(C, F, O, s);
-    else launch_v<real, V, MODE_FIELDS>(C, F, O, s);
 }
 
 template <typename real>
@@ -208,20 +249,11 @@ hipError_t launch_step2d(const Coef<real>& C, const Fields<real>& F, const Field
     }
     if (variant >= Variants2D<real>::count)
         return launch_step2d_march<real>(C, F, O, variant - Variants2D<real>::count, s);
-    switch (variant) {
-    case 0: launch_mode<real, 0>(C, F, O, mode, s); break;
-    case 1: launch_mode<real, 1>(C, F, O, mode, s); break;
-    case 2: launch_mode<real, 2>(C, F, O, mode, s); break;
-    default:
-        if constexpr (Variants2D<real>::count > 3) {
-            if (variant == 3) launch_mode<real, 3>(C, F, O, mode, s);
-            else if (variant == 4) launch_mode<real, 4>(C, F, O, mode, s);
-            else if (variant == 5) launch_mode<real, 5>(C, F, O, mode, s);
-            else return hipErrorInvalidValue;
-        } else {
-            return hipErrorInvalidValue;
-        }
-    }
+    if (variant < 0) return hipErrorInvalidValue;
+    constexpr auto seq = std::make_index_sequence<Variants2D<real>::count>{};
+    static const auto step = table_v<real, MODE_STEP, true>(seq);
+    if (mode == MODE_STEP) step[variant](C, F, O, s);
+    else launch_v<real, 0, MODE_FIELDS, true>(C, F, O, s);
     return hipGetLastError();
 }
 
@@ -244,42 +276,61 @@ static void launch_b(const Coef<real>& C, const BatchArgs<real>& B, int ntiles, 
                        dim3(sh.NT), 0, s, C, B);
 }
 
+template <typename real, size_t... I>
+static auto table_b(std::index_sequence<I...>) {
+    using Fn = void (*)(const Coef<real>&, const BatchArgs<real>&, int, hipStream_t);
+    return std::array<Fn, sizeof...(I)>{&launch_b<real, (int)I>...};
+}
+
 template <typename real>
 hipError_t launch_step2d_batch(const Coef<real>& C, const BatchArgs<real>& B, int ntiles,
                                int variant, hipStream_t s) {
     if (ntiles <= 0) return hipSuccess;
-    switch (variant) {
-    case 0: launch_b<real, 0>(C, B, ntiles, s); break;
-    case 1: launch_b<real, 1>(C, B, ntiles, s); break;
-    case 2: launch_b<real, 2>(C, B, ntiles, s); break;
-    default:
-        if constexpr (Variants2D<real>::count > 3) {
-            if (variant == 3) launch_b<real, 3>(C, B, ntiles, s);
-            else if (variant == 4) launch_b<real, 4>(C, B, ntiles, s);
-            else if (variant == 5) launch_b<real, 5>(C, B, ntiles, s);
-            else return hipErrorInvalidValue;
-        } else {
-            return hipErrorInvalidValue;
-        }
-    }
+    if (variant < 0 || variant >= Variants2D<real>::count) return hipErrorInvalidValue;
+    static const auto tab = table_b<real>(std::make_index_sequence<Variants2D<real>::count>{});
+    tab[variant](C, B, ntiles, s);
     return hipGetLastError();
 }
 
+#if LBM_PREC != 8
 template int tile2d_variants<float>();
+#endif
+#if LBM_PREC != 4
 template int tile2d_variants<double>();
+#endif
+#if LBM_PREC != 8
 template void tile2d_shape<float>(int, int*, int*);
+#endif
+#if LBM_PREC != 4
 template void tile2d_shape<double>(int, int*, int*);
+#endif
+#if LBM_PREC != 8
 template hipError_t launch_step2d_batch<float>(const Coef<float>&, const BatchArgs<float>&, int,
                                                int, hipStream_t);
+#endif
+#if LBM_PREC != 4
 template hipError_t launch_step2d_batch<double>(const Coef<double>&, const BatchArgs<double>&,
                                                 int, int, hipStream_t);
+#endif
+#if LBM_PREC != 8
 template int step2d_variants<float>();
+#endif
+#if LBM_PREC != 4
 template int step2d_variants<double>();
+#endif
+#if LBM_PREC != 8
 template int grid2d_blocks<float>(int, int, int);
+#endif
+#if LBM_PREC != 4
 template int grid2d_blocks<double>(int, int, int);
+#endif
+#if LBM_PREC != 8
 template hipError_t launch_step2d<float>(const Coef<float>&, const Fields<float>&,
                                          const FieldOut<float>&, int, int, hipStream_t);
+#endif
+#if LBM_PREC != 4
 template hipError_t launch_step2d<double>(const Coef<double>&, const Fields<double>&,
                                           const FieldOut<double>&, int, int, hipStream_t);
+#endif
 
 }  // namespace lbm

@@ -18,6 +18,13 @@
 // Only the cross-section halo is re-read; along the sweep axis each slice
 // is read once per chunk, so the re-read fraction is (TZ+4)/TZ * (ring /
 // tile) instead of the cube of a 3-D halo.
+// Built twice: LBM_PREC == 4 holds the FP32 instantiations (compiled with
+// FMA contraction), LBM_PREC == 8 the FP64 ones (no contraction, so that
+// FP64 follows the rounding steps of a plain scalar evaluation).  Without
+// LBM_PREC both are instantiated.
+#ifndef LBM_PREC
+#define LBM_PREC 0
+#endif
 #include "lbm_device.hpp"
 #include "lbm_kernels.hpp"
 
@@ -197,7 +204,10 @@ __global__ __launch_bounds__(TX* TY) void k_step_march(Coef<real> C, Fields<real
                     const int q = own_p + ea + eb * PA;
                     const int s2 = (it - 2 + ec + NPSI) % NPSI;
                     const real w = real(L::w12[a]) * real(1.0 / 12.0);
-                    const real wp = w * s_psi[s2][q];
+                    // FP32: w (psi(x+e) - psi(x)), equal since sum w e = 0,
+                    // with rounding that scales with the psi gradient
+                    const real wp = (sizeof(real) == 4) ? w * (s_psi[s2][q] - psi_c)
+                                                        : w * s_psi[s2][q];
                     const int e3[3] = {L::ex[a], L::ey[a], L::ez[a]};
 #pragma unroll
                     for (int d = 0; d < L::D; ++d) {
@@ -402,19 +412,39 @@ hipError_t launch_step2d_march(const Coef<real>& C, const Fields<real>& F, const
     return hipGetLastError();
 }
 
+#if LBM_PREC != 8
 template int step2d_march_variants<float>();
+#endif
+#if LBM_PREC != 4
 template int step2d_march_variants<double>();
+#endif
+#if LBM_PREC != 8
 template hipError_t launch_step2d_march<float>(const Coef<float>&, const Fields<float>&,
                                                const FieldOut<float>&, int, hipStream_t);
+#endif
+#if LBM_PREC != 4
 template hipError_t launch_step2d_march<double>(const Coef<double>&, const Fields<double>&,
                                                 const FieldOut<double>&, int, hipStream_t);
+#endif
+#if LBM_PREC != 8
 template int step3d_variants<float>();
+#endif
+#if LBM_PREC != 4
 template int step3d_variants<double>();
+#endif
+#if LBM_PREC != 8
 template int grid3d_blocks<float>(int, int, int, int);
+#endif
+#if LBM_PREC != 4
 template int grid3d_blocks<double>(int, int, int, int);
+#endif
+#if LBM_PREC != 8
 template hipError_t launch_step3d<float>(const Coef<float>&, const Fields<float>&,
                                          const FieldOut<float>&, int, int, hipStream_t);
+#endif
+#if LBM_PREC != 4
 template hipError_t launch_step3d<double>(const Coef<double>&, const Fields<double>&,
                                           const FieldOut<double>&, int, int, hipStream_t);
+#endif
 
 }  // namespace lbm

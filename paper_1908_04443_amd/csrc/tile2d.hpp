@@ -116,7 +116,7 @@ __device__ __forceinline__ void d2q9_prologue(const Coef<real>& C, const Fields<
                         first = false;
                     }
                 }
-                const real rave = num / den;
+                const real rave = fdiv(num, den);
                 const int kw = Fd.widx[S.row[ly] + S.col[lx]];
                 // Eq. 16 (phi scales, drho shifts) and the limiter
                 real rw = Fd.phi[kw] * rave - Fd.drho[kw];
@@ -138,6 +138,7 @@ __device__ __forceinline__ void d2q9_prologue(const Coef<real>& C, const Fields<
 
 // Eq. 5 cohesive force and Eq. 8 adhesion at LDS position p; returns the
 // total force F (cohesion + adhesion + body force) and the cohesive part.
+// FP64 sums the terms in the order of Eq. 5.
 template <typename real, int LX>
 __device__ __forceinline__ void d2q9_force(const Coef<real>& C, const uint8_t* cls, const real* psi,
                                            int p, real rho, real* Fm, real* F) {
@@ -148,7 +149,10 @@ __device__ __forceinline__ void d2q9_force(const Coef<real>& C, const uint8_t* c
     for (int a = 1; a < 9; ++a) {
         const int q = p + L::ex[a] + L::ey[a] * LX;
         const real w = real(L::w12[a]) * real(1.0 / 12.0);
-        const real wp = w * psi[q];
+        // FP32 sums w (psi(x+e) - psi(x)) e, equal since sum w e = 0: the
+        // rounding then scales with the psi gradient, not with psi, so the
+        // force in a nearly uniform region keeps its digits
+        const real wp = (sizeof(real) == 4) ? w * (psi[q] - psi_c) : w * psi[q];
         if (L::ex[a] == 1) smx += wp;
         if (L::ex[a] == -1) smx -= wp;
         if (L::ey[a] == 1) smy += wp;

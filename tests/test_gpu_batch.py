@@ -78,7 +78,7 @@ def test_batch_equals_single_bitwise(oracle_mod, gpu_lib, precision):
             assert torch.equal(a[key], c[key]), (i, key)
 
 
-@pytest.mark.parametrize("variant", range(3))  # the FP64 tile shapes
+@pytest.mark.parametrize("variant", range(4))  # the FP64 tile shapes
 def test_batch_every_tile_shape_vs_oracle(oracle_mod, gpu_lib, variant):
     setups = [Setup(oracle_mod, c) for c in _case_dicts(8)]
     b = _batch(gpu_lib, setups, 80, variant=variant)

@@ -2,7 +2,10 @@
 
 Bars: FP64 max-abs on rho <= 1e-12 (after 1000 steps for the 128 x 128
 cylinder-droplet case); FP32 normwise relative on rho <= 1e-4; integer
-results (wall lists) bit-exact.
+results (wall lists) bit-exact.  The FP32 kernels use algebraically equal
+forms that keep FP32 rounding small (collision as an increment of f, force
+from psi differences), so FP32 is compared with the FP64 oracle, not
+bitwise with the FP64 kernels.
 """
 import numpy as np
 import pytest
@@ -51,6 +54,22 @@ def test_c0_fp32_1000_steps(oracle_mod, gpu_lib):
     s = Setup(oracle_mod, dict(C0, precision=4))
     res = run_gpu(gpu_lib, s, 1000)
     _compare(oracle_mod, s, res, 1000, 1e-4, 1e-3, rel=True)
+
+
+def test_c0_fp32_mass_conservation(oracle_mod, gpu_lib):
+    """Halfway bounce-back and the collision conserve mass exactly; in FP32
+    the total over 1000 steps must stay within 1e-7 relative (a collision
+    that re-rounds resting populations every step drifts by ~1e-5)."""
+    s = Setup(oracle_mod, dict(C0, precision=4))
+    res = run_gpu(gpu_lib, s, 0)
+    sol = res["solver"]
+    rc, d0 = sol.diagnostics()
+    sol.step(1000)
+    rc1, d1 = sol.diagnostics()
+    assert rc == 0 and rc1 == 0
+    drift = abs(d1["mass"] - d0["mass"]) / d0["mass"]
+    print(f"FP32 mass drift over 1000 steps {drift:.2e}", flush=True)
+    assert drift <= 1e-7
 
 
 @pytest.mark.parametrize("scheme", ["ivd", "vd", "sfi"])
@@ -126,7 +145,7 @@ def _nvariants(lattice, precision):
 
 
 @pytest.mark.parametrize("precision", [8, 4])
-@pytest.mark.parametrize("variant", range(9))
+@pytest.mark.parametrize("variant", range(16))
 def test_every_d2q9_variant(oracle_mod, gpu_lib, precision, variant):
     if variant >= _nvariants(9, precision):
         pytest.skip("no such variant")
