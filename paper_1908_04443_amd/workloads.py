@@ -20,7 +20,7 @@ import numpy as np
 from . import inputs as I
 
 # Prescribed angle -> (phi, drho) of the improved virtual-density scheme for
-# the Carnahan-Starling fluid at 0.75 Tc (tau = 1, sigma = 0.105).  Angles
+# the Carnahan-Starling fluid at 0.75 Tc (tau = 1, sigma = 0.1071).  Angles
 # below 90 deg use phi >= 1, above 90 deg use drho >= 0 (Sec. III B).
 ANGLE_TABLE_CS075 = {
     "theta": [20.0, 30.0, 45.0, 60.0, 75.0, 90.0, 105.0, 120.0, 135.0, 150.0, 160.0],
@@ -28,7 +28,9 @@ ANGLE_TABLE_CS075 = {
     "drho": [0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.008, 0.016, 0.026, 0.040, 0.052],
 }
 
-SIGMA = {("cs", 0.75, 9): 0.105, ("cs", 0.8, 19): 0.105}
+# sigma of Eq. 7 per (EOS, T/Tc, lattice), from the flat-slab calibration in
+# tests/golden/calibrate_sigma.py (gas density of a slab = Maxwell value).
+SIGMA = {("cs", 0.75, 9): 0.1071, ("pr", 0.86, 9): 0.1115, ("cs", 0.8, 19): 0.1067}
 
 
 def c0_cylinder(rho_g, rho_l, phi=None, drho=None, n=128, R=24, r0=20, noise=1e-6, seed=0):

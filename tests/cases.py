@@ -5,12 +5,19 @@ Model constants (temperature, coexistence densities) come from the oracle,
 never from the GPU library.  Initial fields and geometries come from the
 input generators, which hold no lattice Boltzmann arithmetic.
 """
+import json
+import os
+
 import numpy as np
 
 from paper_1908_04443_amd import inputs as I
 
 SCHEMES = {"ivd": 0, "vd": 1, "sfi": 2}
-SIGMA_CS075 = 0.105  # flat-slab calibration of Eq. 7's sigma, CS at 0.75 Tc (D2Q9, tau = 1)
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+# flat-slab calibration of Eq. 7's sigma (tests/golden/calibrate_sigma.py)
+SIGMA_CAL = json.load(open(os.path.join(GOLDEN, "sigma_calibration.json")))
+SIGMA_CS075 = SIGMA_CAL["cs_0.75"]["sigma"]
+SIGMA_PR086 = SIGMA_CAL["pr_0.86"]["sigma"]
 
 
 def oracle_params(O, case):
