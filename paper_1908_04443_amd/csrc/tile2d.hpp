@@ -21,6 +21,26 @@ struct TileLDS {
     uint32_t row[LY];  // wrapped y * nx of each halo row
 };
 
+// LDS position (lx, ly) of halo-ring entry j: two full rows below the tile,
+// two full rows above, then two columns on each side of each tile row.
+template <int TX, int TY>
+__device__ __forceinline__ void ring_pos(int j, int& lx, int& ly) {
+    constexpr int LX = TX + 4;
+    if (j < 2 * LX) {
+        ly = j / LX;
+        lx = j % LX;
+    } else if (j < 4 * LX) {
+        const int jj = j - 2 * LX;
+        ly = TY + 2 + jj / LX;
+        lx = jj % LX;
+    } else {
+        const int jj = j - 4 * LX;
+        ly = 2 + jj / 4;
+        const int c = jj % 4;
+        lx = c < 2 ? c : TX + c;
+    }
+}
+
 template <typename real, int TX, int TY, int NT, bool BUF>
 __device__ __forceinline__ void d2q9_prologue(const Coef<real>& C, const Fields<real>& Fd,
                                               const PopIO<real, BUF>& io, const int nx,
@@ -35,61 +55,72 @@ __device__ __forceinline__ void d2q9_prologue(const Coef<real>& C, const Fields<
     constexpr int RING = 4 * LX + 4 * TY;
     const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
 
+    // One load phase: node classes, the populations of the owned nodes and
+    // the populations of the halo ring are all issued before any of them is
+    // needed, so a tile waits for one memory round trip instead of two.
+    // Populations are loaded whatever the node class (solid slots are never
+    // used: their density is replaced by 0 below); this costs the lines that
+    // lie wholly inside solid regions and saves a dependent round trip.
+    const bool inner2 = x0 >= 2 && y0 >= 2 && x0 + TX + 2 <= nx && y0 + TY + 2 <= ny;
+    auto node = [&](int lx, int ly) -> uint32_t {
+        if (inner2) return (uint32_t)(y0 - 2 + ly) * (uint32_t)nx + (uint32_t)(x0 - 2 + lx);
+        return (uint32_t)wrapi(y0 - 2 + ly, ny) * (uint32_t)nx + (uint32_t)wrapi(x0 - 2 + lx, nx);
+    };
     for (int i = tid; i < LX + LY; i += NT) {
         if (i < LX) S.col[i] = (uint32_t)wrapi(x0 - 2 + i, nx);
         else S.row[i - LX] = (uint32_t)wrapi(y0 - 2 + (i - LX), ny) * (uint32_t)nx;
     }
-    __syncthreads();
-    for (int i = tid; i < LX * LY; i += NT) {
-        const int lx = i % LX, ly = i / LX;
-        S.cls[i] = Fd.cls[S.row[ly] + S.col[lx]];
-    }
-    __syncthreads();
 
     // owned tile nodes: populations into registers, density into LDS
+    uint8_t oc[RPT];
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+        const int ly = ty + k * ROWS;
+        const uint32_t n = node(tx + 2, ly + 2);
+        oc[k] = Fd.cls[n];
+#pragma unroll
+        for (int a = 0; a < 9; ++a) f[k][a] = io.ld(a, n);
+    }
+    // halo ring: density only
+    constexpr int JR = (RING + NT - 1) / NT;
+    uint8_t rc[JR];
+    real rr[JR];
+#pragma unroll
+    for (int jj = 0; jj < JR; ++jj) {
+        const int j = tid + jj * NT;
+        rc[jj] = CLS_SOLID;
+        rr[jj] = real(0);
+        if (j < RING) {
+            int lx, ly;
+            ring_pos<TX, TY>(j, lx, ly);
+            const uint32_t n = node(lx, ly);
+            rc[jj] = Fd.cls[n];
+            real r = io.ld(0, n);
+#pragma unroll
+            for (int a = 1; a < 9; ++a) r += io.ld(a, n);
+            rr[jj] = r;
+        }
+    }
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
         const int ly = ty + k * ROWS;
         const int p = (ly + 2) * LX + tx + 2;
-        const uint32_t n = S.row[ly + 2] + S.col[tx + 2];
-        real r = real(0);
-        if (S.cls[p] == CLS_FLUID) {
+        real r = f[k][0];
 #pragma unroll
-            for (int a = 0; a < 9; ++a) f[k][a] = io.ld(a, n);
-            r = f[k][0];
-#pragma unroll
-            for (int a = 1; a < 9; ++a) r += f[k][a];
-        } else {
-#pragma unroll
-            for (int a = 0; a < 9; ++a) f[k][a] = real(0);
-        }
-        S.rho[p] = r;
+        for (int a = 1; a < 9; ++a) r += f[k][a];
+        S.cls[p] = oc[k];
+        S.rho[p] = (oc[k] == CLS_FLUID) ? r : real(0);
     }
-    // halo ring: density only
-    for (int j = tid; j < RING; j += NT) {
-        int lx, ly;
-        if (j < 2 * LX) {
-            ly = j / LX;
-            lx = j % LX;
-        } else if (j < 4 * LX) {
-            const int jj = j - 2 * LX;
-            ly = TY + 2 + jj / LX;
-            lx = jj % LX;
-        } else {
-            const int jj = j - 4 * LX;
-            ly = 2 + jj / 4;
-            const int c = jj % 4;
-            lx = c < 2 ? c : TX + c;
-        }
-        const int p = ly * LX + lx;
-        real r = real(0);
-        if (S.cls[p] == CLS_FLUID) {
-            const uint32_t n = S.row[ly] + S.col[lx];
-            r = io.ld(0, n);
 #pragma unroll
-            for (int a = 1; a < 9; ++a) r += io.ld(a, n);
+    for (int jj = 0; jj < JR; ++jj) {
+        const int j = tid + jj * NT;
+        if (j < RING) {
+            int lx, ly;
+            ring_pos<TX, TY>(j, lx, ly);
+            const int p = ly * LX + lx;
+            S.cls[p] = rc[jj];
+            S.rho[p] = (rc[jj] == CLS_FLUID) ? rr[jj] : real(0);
         }
-        S.rho[p] = r;
     }
     __syncthreads();
 
