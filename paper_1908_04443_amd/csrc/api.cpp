@@ -101,6 +101,7 @@ static Fields<real> make_fields(const lbm_ctx* c, int src) {
     F.phi = (const real*)c->phi;
     F.drho = (const real*)c->drho;
     F.flag = c->flag;
+    F.rho = (real*)c->rho;
     return F;
 }
 
@@ -136,7 +137,9 @@ static size_t layout(const lbm_params& p, int64_t nwm, lbm_ctx* c) {
     int32_t* flag = cv.take<int32_t>(4);
     double* part = cv.take<double>(5 * (size_t)nparts);
     double* dout = cv.take<double>(8);
+    void* rho = cv.take<char>((size_t)N * s);  // density pass of the sweep kernels
     if (c) {
+        c->rho = rho;
         c->f[0] = f0;
         c->f[1] = f1;
         c->cls = cls;
@@ -289,6 +292,7 @@ static Fields<real> case_fields(const lbm_ctx* c, const lbm_case& k) {
     F.phi = (const real*)c->phi + k.wall_off;
     F.drho = (const real*)c->drho + k.wall_off;
     F.flag = c->flag;
+    F.rho = (real*)c->rho;
     return F;
 }
 

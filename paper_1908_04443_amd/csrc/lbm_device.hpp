@@ -120,6 +120,8 @@ struct Fields {
     const real* phi;       // per wall node (IVD)
     const real* drho;      // per wall node (IVD)
     int32_t* flag;         // set to 1 when a psi argument is < 0 or NaN
+    real* rho = nullptr;   // density of every node (0 off the fluid), written by
+                           // the density pass that precedes a sweep step
 };
 
 // Workgroups are handed to the 8 XCDs of the chip round-robin by linear id.

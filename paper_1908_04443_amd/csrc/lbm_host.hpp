@@ -92,6 +92,7 @@ struct lbm_ctx {
     int32_t* flag = nullptr;
     double* part = nullptr;
     double* diag_out = nullptr;
+    void* rho = nullptr;  // node densities written by the density pass (sweep kernels)
     int nparts = 0;
     // host state
     lbm::Geometry geom;

@@ -15,9 +15,12 @@
 //      populations are read again here (two iterations after phase A read
 //      them, so they come from L2) instead of being held in registers,
 //      which keeps the register count low enough for several waves per SIMD.
-// Only the cross-section halo is re-read; along the sweep axis each slice
-// is read once per chunk, so the re-read fraction is (TZ+4)/TZ * (ring /
-// tile) instead of the cube of a 3-D halo.
+// The densities of phase A come from a separate density pass (k_density,
+// launched just before): the halo then costs one value per node instead
+// of Q populations, and each node's populations are read once, in phase C.
+// With 19 populations and a 2-node halo around a 32 x 8 cross-section this
+// removes most of the bytes of a 3-D step that sums the halo's
+// populations inside the sweep.
 // Built twice: LBM_PREC == 4 holds the FP32 instantiations (compiled with
 // FMA contraction), LBM_PREC == 8 the FP64 ones (no contraction, so that
 // FP64 follows the rounding steps of a plain scalar evaluation).  Without
@@ -29,6 +32,29 @@
 #include "lbm_kernels.hpp"
 
 namespace lbm {
+
+// Density of every node (Eq. 4), summed in velocity order; 0 off the fluid.
+template <int Q, typename real>
+__global__ __launch_bounds__(256) void k_density(const uint8_t* __restrict__ cls,
+                                                 const real* __restrict__ f, real* __restrict__ rho,
+                                                 uint32_t N) {
+    const uint32_t n = blockIdx.x * 256u + threadIdx.x;
+    if (n >= N) return;
+    real r = real(0);
+    if (cls[n] == CLS_FLUID) {
+        r = f[n];
+#pragma unroll
+        for (int a = 1; a < Q; ++a) r += f[(size_t)a * N + n];
+    }
+    rho[n] = r;
+}
+
+template <int Q, typename real>
+static void launch_density(const Coef<real>& C, const Fields<real>& F, hipStream_t s) {
+    const uint32_t N = (uint32_t)C.nx * (uint32_t)C.ny * (uint32_t)C.nz;
+    hipLaunchKernelGGL((k_density<Q, real>), dim3((N + 255) / 256), dim3(256), 0, s, F.cls, F.fin,
+                       F.rho, N);
+}
 
 template <typename L, typename real, int TX, int TY, int TZ, int MODE, bool XCD, bool BUF>
 __global__ __launch_bounds__(TX* TY) void k_step_march(Coef<real> C, Fields<real> Fd,
@@ -105,25 +131,12 @@ __global__ __launch_bounds__(TX* TY) void k_step_march(Coef<real> C, Fields<real
             const int slot = it % NSLOT;
             const int cz = wrapi(c0 - 2 + it, nc);
             const uint32_t base = (uint32_t)cz * nab;
-            const uint8_t co = Fd.cls[base + own_ab];
-            s_cls[slot][own_p] = co;
-            real r = real(0);
-            if (co == CLS_FLUID) {
-                r = io.ld(0, base + own_ab);
-#pragma unroll
-                for (int a = 1; a < Q; ++a) r += io.ld(a, base + own_ab);
-            }
-            s_rho[slot][own_p] = r;
+            // densities come from the density pass: one value per node
+            s_cls[slot][own_p] = Fd.cls[base + own_ab];
+            s_rho[slot][own_p] = Fd.rho[base + own_ab];
             if (tid < RING) {
-                const uint8_t cr = Fd.cls[base + ring_ab];
-                s_cls[slot][ring_p] = cr;
-                real rr = real(0);
-                if (cr == CLS_FLUID) {
-                    rr = io.ld(0, base + ring_ab);
-#pragma unroll
-                    for (int a = 1; a < Q; ++a) rr += io.ld(a, base + ring_ab);
-                }
-                s_rho[slot][ring_p] = rr;
+                s_cls[slot][ring_p] = Fd.cls[base + ring_ab];
+                s_rho[slot][ring_p] = Fd.rho[base + ring_ab];
             }
         }
         __syncthreads();
@@ -347,6 +360,7 @@ template <typename real>
 hipError_t launch_step3d(const Coef<real>& C, const Fields<real>& F, const FieldOut<real>& O,
                          int mode, int variant, hipStream_t s) {
     if (mode == MODE_FIELDS) variant = 0;
+    launch_density<19, real>(C, F, s);
     // population arrays of 4 GiB or more cannot use 32-bit buffer offsets
     if ((uint64_t)19 * (uint64_t)C.nx * C.ny * C.nz * sizeof(real) > 0xFFFFFFFFull) {
         if (mode == MODE_STEP) launch_v3<real, 0, MODE_STEP, false>(C, F, O, s);
@@ -401,6 +415,7 @@ static void launch_v2m(const Coef<real>& C, const Fields<real>& F, const FieldOu
 template <typename real>
 hipError_t launch_step2d_march(const Coef<real>& C, const Fields<real>& F, const FieldOut<real>& O,
                                int idx, hipStream_t s) {
+    launch_density<9, real>(C, F, s);
     if (idx == 0) launch_v2m<real, 0, MODE_STEP>(C, F, O, s);
     else if constexpr (Variants2M<real>::count > 1) {
         if (idx == 1) launch_v2m<real, 1, MODE_STEP>(C, F, O, s);
