@@ -86,6 +86,7 @@ def run_c1(L, W, steps, warmup):
     solid = data["solid"]
     s, nw = setup_solver(L, W, p, data, int(solid.sum()))
     rc, d0 = s.diagnostics()
+    variant = s.variant
     wall, ms = time_steps(s, warmup, steps)
     rc, d1 = s.diagnostics()
     if rc != 0:
@@ -93,7 +94,7 @@ def run_c1(L, W, steps, warmup):
     N = 2048 * 2048
     nf = int((solid == 0).sum())
     s.close()
-    return dict(N=N, n_fluid=nf, n_wall=nw, wall=wall, ms_events=ms,
+    return dict(N=N, n_fluid=nf, n_wall=nw, wall=wall, ms_events=ms, variant=variant,
                 mass_drift=abs(d1["mass"] - d0["mass"]) / d0["mass"], max_u=d1["max_u"],
                 rho=(d1["rho_min"], d1["rho_max"]), data=data, params=p)
 
@@ -115,9 +116,10 @@ def run_c2(L, W, steps, warmup):
 
 
 def run_c3(L, W, steps, warmup, graph_steps=50):
-    """96 D2Q9 FP32 cases of uneven size: one multi-case context replaying a
-    graph of `graph_steps` steps, against one context per case stepped in
-    turn on the same stream with plain launches."""
+    """96 D2Q9 FP32 cases of uneven size: one multi-case context (tile shape
+    picked by the autotuner) replaying a graph of `graph_steps` steps,
+    against one context per case (its default tile shape) stepped in turn on
+    the same stream with plain launches."""
     import torch
     p = L.make_params(lattice=9, precision=4, nx=1, ny=1, T_ratio=0.75,
                       sigma=W.SIGMA[("cs", 0.75, 9)], tau=1.0)
@@ -134,6 +136,7 @@ def run_c3(L, W, steps, warmup, graph_steps=50):
         b.set_wetting(i, torch.as_tensor(c["phi"].ravel()[w], dtype=b.dtype, device="cuda"),
                       torch.as_tensor(c["drho"].ravel()[w], dtype=b.dtype, device="cuda"))
         b.set_fields(i, c["rho"].ravel())
+    tuned = b.autotune(steps=20)  # tile shape of the multi-case launch
     b.set_graph_steps(graph_steps)
     b.step(warmup)
     torch.cuda.synchronize()
@@ -165,7 +168,7 @@ def run_c3(L, W, steps, warmup, graph_steps=50):
     return dict(total_nodes=total, cases=len(cases), steps=steps,
                 batched_mlups=total * steps / t_batch / 1e6,
                 single_mlups=total * steps / t_single / 1e6,
-                ratio=t_single / t_batch, graph_steps=graph_steps)
+                ratio=t_single / t_batch, graph_steps=graph_steps, batch_tile_variant=tuned)
 
 
 def run_c4(L, W, T=1000, K=50):
@@ -306,7 +309,7 @@ def main():
         "config": {"workload": "D2Q9 MRT pseudopotential 2048x2048 FP32, 400-cylinder "
                                "porous medium, improved virtual density, CS 0.75 Tc",
                    "nx": 2048, "ny": 2048, "lattice": "D2Q9", "fluid_nodes": nf,
-                   "wall_nodes": c1["n_wall"]},
+                   "wall_nodes": c1["n_wall"], "tile_variant": c1["variant"]},
         "mflups": round(nf * args.steps / c1["wall"] / 1e6, 2),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

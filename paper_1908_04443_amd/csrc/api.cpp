@@ -138,8 +138,28 @@ static size_t layout(const lbm_params& p, int64_t nwm, lbm_ctx* c) {
     double* part = cv.take<double>(5 * (size_t)nparts);
     double* dout = cv.take<double>(8);
     void* rho = cv.take<char>((size_t)N * s);  // density pass of the sweep kernels
+    // per-tile wall lists: up to 256 entries per tile of the tile variant
+    // with the most tiles (D2Q9 only)
+    int64_t twcap = 0;
+    if (Q == 9) {
+        const int nv = p.precision == 4 ? tile2d_variants<float>() : tile2d_variants<double>();
+        for (int v = 0; v < nv; ++v) {
+            const int64_t nt = p.precision == 4 ? grid2d_blocks<float>(p.nx, p.ny, v)
+                                                : grid2d_blocks<double>(p.nx, p.ny, v);
+            twcap = nt * 256 > twcap ? nt * 256 : twcap;
+        }
+    }
+    int32_t* twp = cv.take<int32_t>(twcap);
+    int32_t* tww = cv.take<int32_t>(twcap);
+    void* twphi = cv.take<char>(twcap * s);
+    void* twdrho = cv.take<char>(twcap * s);
     if (c) {
         c->rho = rho;
+        c->tw_pack = twp;
+        c->tw_widx = tww;
+        c->tw_phi = twphi;
+        c->tw_drho = twdrho;
+        c->tw_cap = twcap;
         c->f[0] = f0;
         c->f[1] = f1;
         c->cls = cls;
@@ -203,9 +223,21 @@ static hipError_t launch_one(lbm_ctx* c, const Coef<real>& C, int src, hipStream
         B.flag = c->flag;
         B.cases = c->d_cases;
         B.tiles = c->d_tiles;
+        if (c->tw_stride > 0 && c->tw_variant == c->variant) {
+            B.tw_pack = c->tw_pack;
+            B.tw_phi = (const real*)c->tw_phi;
+            B.tw_drho = (const real*)c->tw_drho;
+            B.tw_stride = c->tw_stride;
+        }
         return launch_step2d_batch<real>(C, B, c->ntiles, c->variant, s);
     }
     Fields<real> F = make_fields<real>(c, src);
+    if (c->tw_stride > 0 && c->tw_variant == c->variant) {
+        F.tw_pack = c->tw_pack;
+        F.tw_phi = (const real*)c->tw_phi;
+        F.tw_drho = (const real*)c->tw_drho;
+        F.tw_stride = c->tw_stride;
+    }
     FieldOut<real> O{nullptr, nullptr, nullptr};
     return (c->p.lattice == 9) ? launch_step2d<real>(C, F, O, MODE_STEP, c->variant, s)
                                : launch_step3d<real>(C, F, O, MODE_STEP, c->variant, s);
@@ -246,11 +278,109 @@ static int capture_graph(lbm_ctx* c, const Coef<real>& C) {
     return LBM_OK;
 }
 
+// Per-tile wall lists of the D2Q9 tile step under the improved
+// virtual-density scheme: for every tile, the wall nodes of the tile plus
+// its 1-node ring (the ones whose virtual density the tile forms, Eqs.
+// 16-17) with their LDS positions, so that the step kernel fetches their phi
+// and drho with its first loads instead of through a dependent wall-index
+// lookup.  Entry block t belongs to the t-th tile in the kernel's numbering
+// (row-major for one lattice, table order for a multi-case context).  Lists
+// are off (stride 0) when a tile would hold more than 256 entries or the
+// workspace is too small.
+struct ListTile {
+    const Geometry* g;
+    int nx, ny, x0, y0;
+    int64_t woff;  // offset of the tile's case in the wall-parameter arena
+};
+
+template <typename real>
+static int upload_wall_lists(lbm_ctx* c, const std::vector<ListTile>& tiles, int TX, int TY) {
+    const int LX = TX + 4;
+    const int64_t nt = (int64_t)tiles.size();
+    auto wrap = [](int v, int n) { v %= n; return v < 0 ? v + n : v; };
+    auto node = [&](const ListTile& t, int lx, int ly) {
+        return (int64_t)wrap(t.y0 - 2 + ly, t.ny) * t.nx + wrap(t.x0 - 2 + lx, t.nx);
+    };
+    std::vector<int32_t> cnt(nt, 0);
+    int maxc = 0;
+    for (int64_t i = 0; i < nt; ++i) {
+        int k = 0;
+        for (int ly = 1; ly <= TY + 2; ++ly)
+            for (int lx = 1; lx <= TX + 2; ++lx) k += tiles[i].g->cls[node(tiles[i], lx, ly)] == CLS_WALL;
+        cnt[i] = k;
+        maxc = k > maxc ? k : maxc;
+    }
+    const int stride = maxc <= 64 ? 64 : ((maxc + 63) / 64) * 64;
+    c->tw_variant = c->variant;
+    c->tw_dirty = false;
+    c->graph_dirty = true;
+    c->tw_stride = 0;
+    if (stride > 256 || nt * stride > c->tw_cap) return LBM_OK;
+    std::vector<int32_t> pack(nt * stride), widx(nt * stride, -1);
+    for (int64_t i = 0; i < nt; ++i) {
+        const int64_t e0 = i * stride;
+        const int32_t hi = cnt[i] << 16;
+        int k = 0;
+        for (int ly = 1; ly <= TY + 2; ++ly)
+            for (int lx = 1; lx <= TX + 2; ++lx) {
+                const int64_t n = node(tiles[i], lx, ly);
+                if (tiles[i].g->cls[n] != CLS_WALL) continue;
+                pack[e0 + k] = hi | (ly * LX + lx);
+                widx[e0 + k] = (int32_t)(tiles[i].woff + tiles[i].g->widx[n]);
+                ++k;
+            }
+        for (; k < stride; ++k) pack[e0 + k] = hi | 0xFFFF;
+    }
+    const size_t bytes = (size_t)nt * stride * 4;
+    LBM_HIP(hipMemcpyAsync(c->tw_pack, pack.data(), bytes, hipMemcpyHostToDevice, c->stream));
+    LBM_HIP(hipMemcpyAsync(c->tw_widx, widx.data(), bytes, hipMemcpyHostToDevice, c->stream));
+    LBM_HIP(launch_gather_wall<real>(c->tw_widx, (const real*)c->phi, (const real*)c->drho,
+                                     (real*)c->tw_phi, (real*)c->tw_drho, nt * stride,
+                                     c->stream));
+    LBM_HIP(hipStreamSynchronize(c->stream));  // the host vectors go out of scope
+    c->tw_stride = stride;
+    return LBM_OK;
+}
+
+template <typename real>
+static int ensure_wall_lists(lbm_ctx* c) {
+    const bool want = c->p.lattice == 9 && c->scheme == LBM_WET_IVD &&
+                      c->variant < tile2d_variants<real>() && (c->is_batch || c->have_geom);
+    if (!want) {
+        c->tw_stride = 0;
+        return LBM_OK;
+    }
+    if (!c->tw_dirty && c->tw_variant == c->variant) return LBM_OK;
+    int TX = 0, TY = 0;
+    tile2d_shape<real>(c->variant, &TX, &TY);
+    std::vector<ListTile> t;
+    if (!c->is_batch) {
+        for (int y = 0; y < c->p.ny; y += TY)
+            for (int x = 0; x < c->p.nx; x += TX) t.push_back({&c->geom, c->p.nx, c->p.ny, x, y, 0});
+    } else {
+        // the order of ensure_tiles
+        for (const lbm_case& k : c->cases) {
+            if (!k.have_geom) {
+                c->tw_stride = 0;
+                return LBM_OK;
+            }
+            for (int y = 0; y < k.ny; y += TY)
+                for (int x = 0; x < k.nx; x += TX)
+                    t.push_back({&k.geom, k.nx, k.ny, x, y, (int64_t)k.wall_off});
+        }
+    }
+    return upload_wall_lists<real>(c, t, TX, TY);
+}
+
 template <typename real>
 static int run_steps(lbm_ctx* c, int64_t nsteps) {
     Coef<real> C = make_coef<real>(c);
     if (c->is_batch) {
         int rc = ensure_tiles<real>(c);
+        if (rc != LBM_OK) return rc;
+    }
+    {
+        int rc = ensure_wall_lists<real>(c);
         if (rc != LBM_OK) return rc;
     }
     int64_t done = 0;
@@ -393,6 +523,10 @@ static size_t layout_batch(const lbm_params& p, int ncases, const int32_t* nx, c
     void* drho = cv.take<char>(wall_off * s);
     CaseDesc* dc = cv.take<CaseDesc>(ncases);
     TileRef* dt = cv.take<TileRef>(tiles_max);
+    int32_t* twp = cv.take<int32_t>(tiles_max * 256);  // per-tile wall lists
+    int32_t* tww = cv.take<int32_t>(tiles_max * 256);
+    void* twphi = cv.take<char>(tiles_max * 256 * s);
+    void* twdrho = cv.take<char>(tiles_max * 256 * s);
     int32_t* flag = cv.take<int32_t>(4);
     double* part = cv.take<double>(5 * (size_t)max_parts);
     double* dout = cv.take<double>(8);
@@ -406,6 +540,11 @@ static size_t layout_batch(const lbm_params& p, int ncases, const int32_t* nx, c
         c->d_cases = dc;
         c->d_tiles = dt;
         c->max_tiles = tiles_max;
+        c->tw_pack = twp;
+        c->tw_widx = tww;
+        c->tw_phi = twphi;
+        c->tw_drho = twdrho;
+        c->tw_cap = tiles_max * 256;
         c->flag = flag;
         c->part = part;
         c->diag_out = dout;
@@ -610,6 +749,9 @@ int lbm_create(const lbm_params* p, void* stream, void* workspace, size_t ws_byt
     c->ws_bytes = ws_bytes;
     c->n_wall_max = n_wall_max;
     layout(*p, n_wall_max, c);
+    if (p->lattice == 9)
+        c->variant = p->precision == 4 ? tile2d_preferred_variant<float>()
+                                       : tile2d_preferred_variant<double>();
     if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
         delete c;
         return fail(LBM_EDEVICE, "hipEventCreate failed");
@@ -650,6 +792,7 @@ int lbm_set_geometry(lbm_ctx* c, const uint8_t* solid_host) {
     c->geom = std::move(g);
     c->have_geom = true;
     c->have_fields = false;
+    c->tw_dirty = true;
     c->scheme = LBM_WET_IVD;
     c->scalar = 0.0;
     int rc = (c->prec == 4) ? fill_wetting<float>(c, nullptr, nullptr, 1.0, 0.0)
@@ -705,6 +848,7 @@ int lbm_set_wetting(lbm_ctx* c, int32_t scheme, double scalar, const void* phi_d
     }
     c->scheme = scheme;
     c->scalar = scalar;
+    c->tw_dirty = true;     // the wall lists carry phi and drho
     c->graph_dirty = true;  // the scheme is part of the captured launch arguments
     return LBM_OK;
 }
@@ -1016,6 +1160,7 @@ int lbm_set_geometry_case(lbm_ctx* c, int32_t i, const uint8_t* solid_host) {
     k->geom = std::move(g);
     k->have_geom = true;
     k->have_fields = false;
+    c->tw_dirty = true;
     return LBM_OK;
 }
 
@@ -1049,6 +1194,7 @@ int lbm_set_wetting_case(lbm_ctx* c, int32_t i, const void* phi_dev, const void*
     if (drho_dev) LBM_HIP(hipMemcpyAsync(dr, drho_dev, bytes, hipMemcpyDeviceToDevice, c->stream));
     else if (c->prec == 4) LBM_HIP(launch_fill<float>((float*)dr, (float)drho0, nw, c->stream));
     else LBM_HIP(launch_fill<double>((double*)dr, drho0, nw, c->stream));
+    c->tw_dirty = true;  // the wall lists carry copies of phi and drho
     return LBM_OK;
 }
 

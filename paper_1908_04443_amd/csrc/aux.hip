@@ -72,7 +72,29 @@ __global__ void k_diag_final(const double* __restrict__ part, int nparts, double
     }
 }
 
+// wall parameters of the per-tile wall lists: out[e] = in[widx[e]] (0 where
+// the entry is empty)
+template <typename real>
+__global__ void k_gather_wall(const int32_t* __restrict__ widx, const real* __restrict__ phi,
+                              const real* __restrict__ drho, real* __restrict__ ophi,
+                              real* __restrict__ odrho, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t k = widx[i];
+    ophi[i] = k >= 0 ? phi[k] : real(0);
+    odrho[i] = k >= 0 ? drho[k] : real(0);
+}
+
 static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+template <typename real>
+hipError_t launch_gather_wall(const int32_t* widx, const real* phi, const real* drho, real* ophi,
+                              real* odrho, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_gather_wall<real>), dim3(nblk(n, 256)), dim3(256), 0, s, widx, phi, drho,
+                       ophi, odrho, n);
+    return hipGetLastError();
+}
 
 template <typename real>
 hipError_t launch_init_eq(int lattice, const uint8_t* cls, const real* rho, const real* u,
@@ -118,5 +140,9 @@ template hipError_t launch_mask_solid<float>(int, const uint8_t*, float*, int64_
 template hipError_t launch_mask_solid<double>(int, const uint8_t*, double*, int64_t, hipStream_t);
 template hipError_t launch_fill<float>(float*, float, int64_t, hipStream_t);
 template hipError_t launch_fill<double>(double*, double, int64_t, hipStream_t);
+template hipError_t launch_gather_wall<float>(const int32_t*, const float*, const float*, float*,
+                                              float*, int64_t, hipStream_t);
+template hipError_t launch_gather_wall<double>(const int32_t*, const double*, const double*,
+                                               double*, double*, int64_t, hipStream_t);
 
 }  // namespace lbm

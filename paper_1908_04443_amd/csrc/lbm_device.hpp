@@ -122,6 +122,15 @@ struct Fields {
     int32_t* flag;         // set to 1 when a psi argument is < 0 or NaN
     real* rho = nullptr;   // density of every node (0 off the fluid), written by
                            // the density pass that precedes a sweep step
+    // Per-tile wall lists of the D2Q9 tile step (improved virtual density):
+    // tile t owns entries [t * tw_stride, (t + 1) * tw_stride); each entry
+    // packs (wall count of the tile << 16) | LDS position of one wall node
+    // of the tile plus its 1-node ring (0xFFFF past the count), with that
+    // wall's phi and drho beside it.  tw_pack == nullptr: no lists.
+    const int32_t* tw_pack = nullptr;
+    const real* tw_phi = nullptr;
+    const real* tw_drho = nullptr;
+    int tw_stride = 0;
 };
 
 // Workgroups are handed to the 8 XCDs of the chip round-robin by linear id.

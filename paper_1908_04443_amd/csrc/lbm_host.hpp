@@ -94,6 +94,15 @@ struct lbm_ctx {
     double* diag_out = nullptr;
     void* rho = nullptr;  // node densities written by the density pass (sweep kernels)
     int nparts = 0;
+    // per-tile wall lists of the D2Q9 tile step (see Fields::tw_pack)
+    int32_t* tw_pack = nullptr;
+    int32_t* tw_widx = nullptr;  // wall-list index of each entry, -1 when empty
+    void* tw_phi = nullptr;
+    void* tw_drho = nullptr;
+    int64_t tw_cap = 0;     // entries available in the workspace
+    int tw_stride = 0;      // entries per tile of the current lists (0: none)
+    int tw_variant = -1;    // tile variant the lists were built for
+    bool tw_dirty = true;   // geometry, wetting or variant changed since
     // host state
     lbm::Geometry geom;
     bool have_geom = false, have_fields = false, domain_error = false;

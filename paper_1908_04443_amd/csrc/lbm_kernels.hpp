@@ -44,6 +44,11 @@ struct BatchArgs {
     int32_t* flag;
     const CaseDesc* cases;
     const TileRef* tiles;
+    // per-tile wall lists, indexed by tile-table position (see Fields)
+    const int32_t* tw_pack = nullptr;
+    const real* tw_phi = nullptr;
+    const real* tw_drho = nullptr;
+    int tw_stride = 0;
 };
 
 // wave64 butterfly reduction followed by a fixed-order pass over the waves of
@@ -107,6 +112,8 @@ hipError_t launch_step2d(const Coef<real>& C, const Fields<real>& F, const Field
 template <typename real>
 int tile2d_variants();
 template <typename real>
+int tile2d_preferred_variant();
+template <typename real>
 void tile2d_shape(int variant, int* TX, int* TY);
 template <typename real>
 hipError_t launch_step2d_batch(const Coef<real>& C, const BatchArgs<real>& B, int ntiles,
@@ -154,6 +161,9 @@ hipError_t launch_mask_solid(int Q, const uint8_t* cls, real* f, int64_t N, hipS
 template <typename real>
 hipError_t launch_fill(real* p, real v, int64_t n, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+template <typename real>
+hipError_t launch_gather_wall(const int32_t* widx, const real* phi, const real* drho, real* ophi,
+                              real* odrho, int64_t n, hipStream_t s);
 hipError_t launch_diag_final(const double* part, int nparts, double* out, hipStream_t s);
 
 }  // namespace lbm

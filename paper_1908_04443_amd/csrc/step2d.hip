@@ -35,11 +35,12 @@ namespace lbm {
 
 // The work of one TX x TY tile at (x0, y0) of an nx x ny lattice; shared by
 // the single-lattice kernel and the multi-case kernel.  part: index of this
-// tile's diagnostic partial.
+// tile's diagnostic partial; list_tile: its entry block in the wall lists.
 template <typename real, int TX, int TY, int NT, int MODE, bool BUF>
 __device__ __forceinline__ void d2q9_tile(const Coef<real>& C, const Fields<real>& Fd,
                                           const FieldOut<real>& Out, const int nx, const int ny,
-                                          const int x0, const int y0, const int part) {
+                                          const int x0, const int y0, const int part,
+                                          const int list_tile) {
     using L = D2Q9;
     constexpr int LX = TX + 4;
     constexpr int ROWS = NT / TX;
@@ -50,7 +51,7 @@ __device__ __forceinline__ void d2q9_tile(const Coef<real>& C, const Fields<real
     const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
     bool bad = false;
     real f[RPT][9];
-    d2q9_prologue<real, TX, TY, NT, BUF>(C, Fd, io, nx, ny, x0, y0, S, f, bad);
+    d2q9_prologue<real, TX, TY, NT, BUF>(C, Fd, io, nx, ny, x0, y0, list_tile, S, f, bad);
 
     double d_sum = 0.0;
     real d_umax = real(0), d_rmin = real(1e30), d_rmax = real(-1e30);
@@ -151,7 +152,8 @@ __global__ __launch_bounds__(NT, OCC) void k_step_d2q9(Coef<real> C, Fields<real
         bx = bid % gxb;
         by = bid / gxb;
     }
-    d2q9_tile<real, TX, TY, NT, MODE, BUF>(C, Fd, Out, C.nx, C.ny, bx * TX, by * TY, bid);
+    d2q9_tile<real, TX, TY, NT, MODE, BUF>(C, Fd, Out, C.nx, C.ny, bx * TX, by * TY, bid,
+                                           by * gxb + bx);
 }
 
 // Many independent lattices in one launch: workgroup -> (case, tile) through
@@ -170,8 +172,12 @@ __global__ __launch_bounds__(NT) void k_step_d2q9_batch(Coef<real> C, BatchArgs<
     Fd.phi = B.phi + cd.wall_off;
     Fd.drho = B.drho + cd.wall_off;
     Fd.flag = B.flag;
+    Fd.tw_pack = B.tw_pack;
+    Fd.tw_phi = B.tw_phi;
+    Fd.tw_drho = B.tw_drho;
+    Fd.tw_stride = B.tw_stride;
     FieldOut<real> none{nullptr, nullptr, nullptr};
-    d2q9_tile<real, TX, TY, NT, MODE_STEP, BUF>(C, Fd, none, cd.nx, cd.ny, t.x0, t.y0, bid);
+    d2q9_tile<real, TX, TY, NT, MODE_STEP, BUF>(C, Fd, none, cd.nx, cd.ny, t.x0, t.y0, bid, bid);
 }
 
 // ----------------------------------------------------------------- launch
@@ -189,6 +195,7 @@ struct Variants2D;
 template <>
 struct Variants2D<float> {
     static constexpr int count = 12;
+    static constexpr int preferred = 10;  // 128 x 16 tiles, 512 threads
     static constexpr Shape2D shape[count] = {
         {64, 16, 256, true, 0, 1},  {64, 16, 256, false, 0, 1}, {128, 8, 256, true, 0, 1},
         {64, 32, 256, true, 0, 1},  {256, 4, 256, true, 0, 1},  {128, 16, 256, true, 0, 1},
@@ -198,6 +205,7 @@ struct Variants2D<float> {
 template <>
 struct Variants2D<double> {
     static constexpr int count = 4;
+    static constexpr int preferred = 0;
     static constexpr Shape2D shape[count] = {{64, 8, 256, true, 0, 1},
                                              {64, 8, 256, false, 0, 1},
                                              {128, 4, 256, true, 0, 1},
@@ -262,6 +270,13 @@ int tile2d_variants() {
     return Variants2D<real>::count;
 }
 
+// the variant a single-lattice context starts with (fastest on the 2048^2
+// porous benchmark lattice); the autotuner may pick another
+template <typename real>
+int tile2d_preferred_variant() {
+    return Variants2D<real>::preferred;
+}
+
 template <typename real>
 void tile2d_shape(int variant, int* TX, int* TY) {
     const Shape2D sh = Variants2D<real>::shape[variant];
@@ -294,9 +309,11 @@ hipError_t launch_step2d_batch(const Coef<real>& C, const BatchArgs<real>& B, in
 
 #if LBM_PREC != 8
 template int tile2d_variants<float>();
+template int tile2d_preferred_variant<float>();
 #endif
 #if LBM_PREC != 4
 template int tile2d_variants<double>();
+template int tile2d_preferred_variant<double>();
 #endif
 #if LBM_PREC != 8
 template void tile2d_shape<float>(int, int*, int*);

@@ -19,6 +19,7 @@ struct TileLDS {
     real psi[LX * LY];
     uint32_t col[LX];  // wrapped x of each halo column
     uint32_t row[LY];  // wrapped y * nx of each halo row
+    int wl_count;      // wall-list length of the tile
 };
 
 // LDS position (lx, ly) of halo-ring entry j: two full rows below the tile,
@@ -45,7 +46,7 @@ template <typename real, int TX, int TY, int NT, bool BUF>
 __device__ __forceinline__ void d2q9_prologue(const Coef<real>& C, const Fields<real>& Fd,
                                               const PopIO<real, BUF>& io, const int nx,
                                               const int ny, const int x0, const int y0,
-                                              TileLDS<real, TX, TY>& S,
+                                              const int list_tile, TileLDS<real, TX, TY>& S,
                                               real (&f)[TY / (NT / TX)][9], bool& bad) {
     using L = D2Q9;
     constexpr int LX = TX + 4, LY = TY + 4;
@@ -69,6 +70,24 @@ __device__ __forceinline__ void d2q9_prologue(const Coef<real>& C, const Fields<
     for (int i = tid; i < LX + LY; i += NT) {
         if (i < LX) S.col[i] = (uint32_t)wrapi(x0 - 2 + i, nx);
         else S.row[i - LX] = (uint32_t)wrapi(y0 - 2 + (i - LX), ny) * (uint32_t)nx;
+    }
+
+    // Per-tile wall list (improved virtual density): the first wave loads
+    // the first 64 entries with the other loads of this phase; entries
+    // beyond 64 (rare) follow after the barrier.
+    const bool wl_on = C.scheme == WET_IVD && Fd.tw_pack != nullptr;
+    uint32_t wl_e0 = 0;
+    int wl_pos = -1;
+    real wl_phi = real(0), wl_drho = real(0);
+    if (wl_on) {
+        wl_e0 = (uint32_t)list_tile * (uint32_t)Fd.tw_stride;
+        if (tid < 64) {
+            const int w = Fd.tw_pack[wl_e0 + tid];
+            wl_phi = Fd.tw_phi[wl_e0 + tid];
+            wl_drho = Fd.tw_drho[wl_e0 + tid];
+            if (tid < (w >> 16)) wl_pos = w & 0xFFFF;
+            if (tid == 0) S.wl_count = w >> 16;
+        }
     }
 
     // owned tile nodes: populations into registers, density into LDS
@@ -124,12 +143,21 @@ __device__ __forceinline__ void d2q9_prologue(const Coef<real>& C, const Fields<
     }
     __syncthreads();
 
+    // wall-list entries beyond the first 64
+    if (wl_on && tid >= 64 && tid < S.wl_count) {
+        wl_pos = Fd.tw_pack[wl_e0 + tid] & 0xFFFF;
+        wl_phi = Fd.tw_phi[wl_e0 + tid];
+        wl_drho = Fd.tw_drho[wl_e0 + tid];
+    }
+
     // psi on tile + 1 halo; wall nodes first get their virtual density
+    // (with a wall list, the listed walls are done below by their entries)
     for (int i = tid; i < (TX + 2) * (TY + 2); i += NT) {
         const int lx = 1 + i % (TX + 2), ly = 1 + i / (TX + 2);
         const int p = ly * LX + lx;
         const uint8_t c = S.cls[p];
         real ps = real(0);
+        if (c == CLS_WALL && wl_on) continue;
         if (c == CLS_FLUID) {
             ps = psi_of(C, S.rho[p], bad);
         } else if (c == CLS_WALL) {
@@ -163,6 +191,27 @@ __device__ __forceinline__ void d2q9_prologue(const Coef<real>& C, const Fields<
             }
         }
         S.psi[p] = ps;
+    }
+    if (wl_pos >= 0) {
+        // Eq. 17 over the fluid neighbours, Eq. 16 and the limiter
+        const int p = wl_pos;
+        real num = real(0), den = real(0);
+        bool first = true;
+#pragma unroll
+        for (int a = 1; a < 9; ++a) {
+            const int q = p + L::ex[a] + L::ey[a] * LX;
+            if (S.cls[q] == CLS_FLUID) {
+                const real w = real(L::w12[a]) * real(1.0 / 12.0);
+                num = first ? w * S.rho[q] : num + w * S.rho[q];
+                den = first ? w : den + w;
+                first = false;
+            }
+        }
+        real rw = wl_phi * fdiv(num, den) - wl_drho;
+        rw = rw > C.rho_l ? C.rho_l : rw;
+        rw = rw < C.rho_g ? C.rho_g : rw;
+        S.rho[p] = rw;
+        S.psi[p] = psi_of(C, rw, bad);
     }
     __syncthreads();
 }
