@@ -332,7 +332,7 @@ def main():
             "achieved_GBs": round(b2 / k2 / 1e9, 1),
             "frac": round(b2 / k2 / 1e9 / HBM_PEAK_GBS, 4),
             "kernel_ms": round(k2 * 1e3, 5), "steps": args.c2_steps,
-            "traffic": measured_traffic("k_step_march", "c2")}
+            "traffic": measured_traffic("d3q19_step", "c2")}
         log(f"C2: {out['secondary']['d3q19_256cubed_fp32']}")
     if "c3" in want:
         log(f"C3: 96 uneven D2Q9 FP32 cases, {args.c3_steps} steps, batched vs one per launch")
