@@ -752,6 +752,9 @@ int lbm_create(const lbm_params* p, void* stream, void* workspace, size_t ws_byt
     if (p->lattice == 9)
         c->variant = p->precision == 4 ? tile2d_preferred_variant<float>()
                                        : tile2d_preferred_variant<double>();
+    else
+        c->variant = p->precision == 4 ? step3d_preferred_variant<float>()
+                                       : step3d_preferred_variant<double>();
     if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
         delete c;
         return fail(LBM_EDEVICE, "hipEventCreate failed");

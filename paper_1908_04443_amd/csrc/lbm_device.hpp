@@ -387,6 +387,111 @@ __device__ __forceinline__ void collide_d2q9_f32(const Coef<float>& C, const flo
     fs[8] = f[8] + ((cd - xy1) - (Py - Px));
 }
 
+// FP32 D3Q19 collision: the d'Humieres rows factored into sums and
+// differences of opposite-velocity pairs (axis pairs; xy, xz and yz
+// face-diagonal pairs), the increment form f* = f + M^-1 (m* - m), and one
+// reciprocal of rho; same m = M f, relaxation (grouped rates), forcing
+// (M G of the Guo force plus the sigma term on the energy row) and
+// M^-1 = M^T diag(1/norm) as the row-by-row form below.
+__device__ __forceinline__ void collide_d3q19_f32(const Coef<float>& C, const float* f, float rho,
+                                                  const float* F, const float* Fm, float psi,
+                                                  float* fs, float* u_out) {
+    const float sx = f[1] + f[2], dx = f[1] - f[2];
+    const float sy = f[3] + f[4], dy = f[3] - f[4];
+    const float sz = f[5] + f[6], dz = f[5] - f[6];
+    const float s78 = f[7] + f[8], d78 = f[7] - f[8];
+    const float s910 = f[9] + f[10], d910 = f[9] - f[10];
+    const float s1112 = f[11] + f[12], d1112 = f[11] - f[12];
+    const float s1314 = f[13] + f[14], d1314 = f[13] - f[14];
+    const float s1516 = f[15] + f[16], d1516 = f[15] - f[16];
+    const float s1718 = f[17] + f[18], d1718 = f[17] - f[18];
+    const float Sxy = s78 + s910, Sxz = s1112 + s1314, Syz = s1516 + s1718;
+    const float Sax = sx + sy + sz, Sdg = Sxy + Sxz + Syz;
+    const float m_e = 8.0f * Sdg - 11.0f * Sax - 30.0f * f[0];
+    const float m_eps = Sdg - 4.0f * Sax + 12.0f * f[0];
+    const float Dx = (d78 + d910) + (d1112 + d1314);
+    const float Dy = (d78 - d910) + (d1516 + d1718);
+    const float Dz = (d1112 - d1314) + (d1516 - d1718);
+    const float jx = dx + Dx, jy = dy + Dy, jz = dz + Dz;
+    const float qx = Dx - 4.0f * dx, qy = Dy - 4.0f * dy, qz = Dz - 4.0f * dz;
+    const float A9 = Sxy + Sxz - 2.0f * Syz;
+    const float p9 = (2.0f * sx - sy - sz) + A9, p10 = (2.0f * (sy + sz) - 4.0f * sx) + A9;
+    const float B11 = Sxy - Sxz;
+    const float p11 = (sy - sz) + B11, p12 = 2.0f * (sz - sy) + B11;
+    const float pxy = s78 - s910, pyz = s1516 - s1718, pxz = s1112 - s1314;
+    const float mx = (d78 + d910) - (d1112 + d1314);
+    const float my = (d910 - d78) + (d1516 + d1718);
+    const float mz = (d1112 - d1314) - (d1516 - d1718);
+
+    const float inv = __builtin_amdgcn_rcpf(rho);
+    const float ux = (jx + 0.5f * F[0]) * inv, uy = (jy + 0.5f * F[1]) * inv;
+    const float uz = (jz + 0.5f * F[2]) * inv;
+    u_out[0] = ux;
+    u_out[1] = uy;
+    u_out[2] = uz;
+    const float uF = ux * F[0] + uy * F[1] + uz * F[2];
+    const float u2 = ux * ux + uy * uy + uz * uz;
+    const float fm2 = Fm[0] * Fm[0] + Fm[1] * Fm[1] + Fm[2] * Fm[2];
+    const float sgm = (psi > 0.0f) ? fdiv(fm2, psi * psi) : 0.0f;
+
+    const float se = C.s[GRP_E], sp = C.s[GRP_EPS], sq = C.s[GRP_Q];
+    const float sn = C.s[GRP_NU], spi = C.s[GRP_PI], sm = C.s[GRP_M];
+    const float hq = 1.0f - 0.5f * sq, hn = 1.0f - 0.5f * sn, hp = 1.0f - 0.5f * spi;
+    // m* - m = s (m_eq - m) + (1 - s/2) Src per row
+    const float de = se * (rho * (19.0f * u2 - 11.0f) - m_e) +
+                     (1.0f - 0.5f * se) * (38.0f * uF + C.sig_e * sgm);
+    const float dp = sp * (rho * (3.0f - 5.5f * u2) - m_eps) - (1.0f - 0.5f * sp) * (11.0f * uF);
+    const float t23 = 2.0f / 3.0f;
+    const float dqx = -sq * (t23 * rho * ux + qx) - hq * (t23 * F[0]);
+    const float dqy = -sq * (t23 * rho * uy + qy) - hq * (t23 * F[1]);
+    const float dqz = -sq * (t23 * rho * uz + qz) - hq * (t23 * F[2]);
+    const float T9 = 2.0f * ux * ux - uy * uy - uz * uz;
+    const float G9 = 2.0f * ux * F[0] - uy * F[1] - uz * F[2];
+    const float T11 = uy * uy - uz * uz, G11 = uy * F[1] - uz * F[2];
+    const float d9 = sn * (rho * T9 - p9) + hn * 2.0f * G9;
+    const float d10 = spi * (-0.5f * rho * T9 - p10) - hp * G9;
+    const float d11 = sn * (rho * T11 - p11) + hn * 2.0f * G11;
+    const float d12 = spi * (-0.5f * rho * T11 - p12) - hp * G11;
+    const float dxy = sn * (rho * ux * uy - pxy) + hn * (ux * F[1] + uy * F[0]);
+    const float dyz = sn * (rho * uy * uz - pyz) + hn * (uy * F[2] + uz * F[1]);
+    const float dxz = sn * (rho * ux * uz - pxz) + hn * (ux * F[2] + uz * F[0]);
+
+    // f* - f = M^T diag(1/norm) (m* - m)
+    const float E = de * (1.0f / 2394.0f), P = dp * (1.0f / 252.0f);
+    const float JX = F[0] * 0.1f, JY = F[1] * 0.1f, JZ = F[2] * 0.1f;
+    const float QX = dqx * (1.0f / 40.0f), QY = dqy * (1.0f / 40.0f), QZ = dqz * (1.0f / 40.0f);
+    const float X9 = d9 * (1.0f / 36.0f), X10 = d10 * (1.0f / 72.0f);
+    const float W11 = d11 * (1.0f / 12.0f), W12 = d12 * (1.0f / 24.0f);
+    const float Pxy = dxy * 0.25f, Pyz = dyz * 0.25f, Pxz = dxz * 0.25f;
+    const float Mx = -sm * mx * 0.125f, My = -sm * my * 0.125f, Mz = -sm * mz * 0.125f;
+    fs[0] = f[0] + (12.0f * P - 30.0f * E);
+    const float ba = -11.0f * E - 4.0f * P;
+    const float c9 = 2.0f * X9 - 4.0f * X10, c9h = 2.0f * X10 - X9;
+    const float ax = JX - 4.0f * QX, ay = JY - 4.0f * QY, az = JZ - 4.0f * QZ;
+    const float wyz = W11 - 2.0f * W12;
+    fs[1] = f[1] + ((ba + c9) + ax);
+    fs[2] = f[2] + ((ba + c9) - ax);
+    fs[3] = f[3] + ((ba + c9h + wyz) + ay);
+    fs[4] = f[4] + ((ba + c9h + wyz) - ay);
+    fs[5] = f[5] + ((ba + c9h - wyz) + az);
+    fs[6] = f[6] + ((ba + c9h - wyz) - az);
+    const float bd = 8.0f * E + P, X = X9 + X10, Wt = W11 + W12;
+    const float Lx = JX + QX, Ly = JY + QY, Lz = JZ + QZ;
+    const float bxy = bd + X + Wt, bxz = bd + X - Wt, byz = bd - 2.0f * X;
+    fs[7] = f[7] + ((bxy + Pxy) + ((Lx + Ly) + (Mx - My)));
+    fs[8] = f[8] + ((bxy + Pxy) - ((Lx + Ly) + (Mx - My)));
+    fs[9] = f[9] + ((bxy - Pxy) + ((Lx - Ly) + (Mx + My)));
+    fs[10] = f[10] + ((bxy - Pxy) - ((Lx - Ly) + (Mx + My)));
+    fs[11] = f[11] + ((bxz + Pxz) + ((Lx + Lz) + (Mz - Mx)));
+    fs[12] = f[12] + ((bxz + Pxz) - ((Lx + Lz) + (Mz - Mx)));
+    fs[13] = f[13] + ((bxz - Pxz) + ((Lx - Lz) - (Mx + Mz)));
+    fs[14] = f[14] + ((bxz - Pxz) - ((Lx - Lz) - (Mx + Mz)));
+    fs[15] = f[15] + ((byz + Pyz) + ((Ly + Lz) + (My - Mz)));
+    fs[16] = f[16] + ((byz + Pyz) - ((Ly + Lz) + (My - Mz)));
+    fs[17] = f[17] + ((byz - Pyz) + ((Ly - Lz) + (My + Mz)));
+    fs[18] = f[18] + ((byz - Pyz) - ((Ly - Lz) + (My + Mz)));
+}
+
 // Post-collision populations of one fluid node (Eq. 2, forcing of Eq. 7):
 // m = M f, m* = m - S (m - m_eq) + (I - S/2) Src, f* = M^-1 m*.
 // in: f (populations), rho, F (total force), Fm (cohesive force of Eq. 5),
@@ -398,6 +503,10 @@ __device__ __forceinline__ void collide(const Coef<real>& C, const real* f, real
                                         real* fs, real* u_out) {
     if constexpr (L::Q == 9 && sizeof(real) == 4) {
         collide_d2q9_f32(C, f, rho, F, Fm, psi, fs, u_out);
+        return;
+    }
+    if constexpr (L::Q == 19 && sizeof(real) == 4) {
+        collide_d3q19_f32(C, f, rho, F, Fm, psi, fs, u_out);
         return;
     }
     constexpr int Q = L::Q;

@@ -126,6 +126,8 @@ hipError_t launch_step2d_march(const Coef<real>& C, const Fields<real>& F, const
 template <typename real>
 int step3d_variants();
 template <typename real>
+int step3d_preferred_variant();
+template <typename real>
 int grid3d_blocks(int nx, int ny, int nz, int variant);
 template <typename real>
 hipError_t launch_step3d(const Coef<real>& C, const Fields<real>& F, const FieldOut<real>& O,

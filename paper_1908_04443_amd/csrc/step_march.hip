@@ -320,18 +320,26 @@ struct Variants3D;
 template <>
 struct Variants3D<float> {
     static constexpr int count = 5;
+    static constexpr int preferred = 2;  // 32 x 8 cross-section, chunks of 8 slices
     static constexpr Shape3D shape[count] = {
         {32, 8, 16, true}, {32, 8, 16, false}, {32, 8, 8, true}, {32, 8, 32, true}, {16, 16, 16, true}};
 };
 template <>
 struct Variants3D<double> {
     static constexpr int count = 2;
+    static constexpr int preferred = 0;
     static constexpr Shape3D shape[count] = {{32, 8, 16, true}, {32, 8, 16, false}};
 };
 
 template <typename real>
 int step3d_variants() {
     return Variants3D<real>::count;
+}
+
+// the variant a D3Q19 context starts with (fastest on the 256^3 benchmark)
+template <typename real>
+int step3d_preferred_variant() {
+    return Variants3D<real>::preferred;
 }
 
 template <typename real>
@@ -443,9 +451,11 @@ template hipError_t launch_step2d_march<double>(const Coef<double>&, const Field
 #endif
 #if LBM_PREC != 8
 template int step3d_variants<float>();
+template int step3d_preferred_variant<float>();
 #endif
 #if LBM_PREC != 4
 template int step3d_variants<double>();
+template int step3d_preferred_variant<double>();
 #endif
 #if LBM_PREC != 8
 template int grid3d_blocks<float>(int, int, int, int);
