@@ -1,5 +1,6 @@
 """Host-side post-processing of density fields: liquid-gas interface points,
-circle fits and static contact angles on flat and cylindrical walls.
+circle and sphere fits, static contact angles on flat, cylindrical and
+spherical walls.
 
 Plain numpy on arrays copied to the host; no lattice Boltzmann arithmetic.
 Conventions: a 2-D field is indexed [y, x]; node (x, y) sits at integer
@@ -121,3 +122,57 @@ def bulk_densities(rho, center, r_in, r_out_min):
     dy = np.minimum(dy, ny - dy)
     d = np.hypot(dx, dy)
     return float(rho[d <= r_in].mean()), float(rho[d >= r_out_min].mean())
+
+
+def interface_points_3d(rho, level, solid=None):
+    """3-D version of interface_points for a field indexed [z, y, x]:
+    crossings of `level` along x, y and z links between two fluid nodes.
+    Returns an (n, 3) array of (x, y, z)."""
+    rho = np.asarray(rho, dtype=np.float64)
+    fluid = np.ones_like(rho, bool) if solid is None else (np.asarray(solid) == 0)
+    d = rho - level
+    pts = []
+    for axis in (2, 1, 0):  # x, y, z
+        sl0 = [slice(None)] * 3
+        sl1 = [slice(None)] * 3
+        sl0[axis] = slice(None, -1)
+        sl1[axis] = slice(1, None)
+        a, b = d[tuple(sl0)], d[tuple(sl1)]
+        ok = fluid[tuple(sl0)] & fluid[tuple(sl1)] & (a * b < 0)
+        zz, yy, xx = np.nonzero(ok)
+        t = a[zz, yy, xx] / (a[zz, yy, xx] - b[zz, yy, xx])
+        c = np.stack([xx, yy, zz], axis=1).astype(float)
+        c[:, 2 - axis] += t
+        pts.append(c)
+    return np.concatenate(pts, axis=0)
+
+
+def fit_sphere(pts):
+    """Algebraic least-squares sphere through (x, y, z) points: returns
+    (cx, cy, cz, r)."""
+    A = np.concatenate([pts, np.ones((len(pts), 1))], axis=1)
+    rhs = -(pts ** 2).sum(axis=1)
+    (D, E, F, G), *_ = np.linalg.lstsq(A, rhs, rcond=None)
+    c = -0.5 * np.array([D, E, F])
+    return float(c[0]), float(c[1]), float(c[2]), float(np.sqrt(c @ c - G))
+
+
+def contact_angle_sphere(rho, solid, center, R_nodes, rho_g, rho_l, min_wall_dist=4.0,
+                         level=None, select=None):
+    """Static contact angle of a droplet on a sphere of node radius R_nodes
+    centred at `center` (x, y, z), field indexed [z, y, x]: a sphere fitted
+    to the droplet interface (points at least `min_wall_dist` from the wall
+    surface of radius R_nodes + 1/2) meets the wall sphere at the angle of
+    angle_between_circles.  Returns (theta_deg, (cx, cy, cz, r, npoints))."""
+    Rw = R_nodes + 0.5
+    lev = droplet_level(rho_g, rho_l) if level is None else level
+    p = interface_points_3d(rho, lev, solid)
+    c0 = np.asarray(center, dtype=float)
+    p = p[np.linalg.norm(p - c0, axis=1) - Rw >= min_wall_dist]
+    if select is not None and len(p):
+        p = p[select(p[:, 0], p[:, 1], p[:, 2])]
+    if len(p) < 16:
+        raise ValueError("too few interface points for a sphere fit")
+    cx, cy, cz, r = fit_sphere(p)
+    dist = float(np.linalg.norm(np.array([cx, cy, cz]) - c0))
+    return angle_between_circles(r, Rw, dist), (cx, cy, cz, r, len(p))

@@ -27,6 +27,7 @@ CASES = {
     "cs_0.75": (dict(eos=0, a=1.0, b=4.0), 0.75, 1.0, 9),
     "pr_0.86": (dict(eos=1, a=2.0 / 49.0, b=2.0 / 21.0), 0.86, 1.0, 9),
     "cs_0.80_d3q19": (dict(eos=0, a=1.0, b=4.0), 0.80, 1.0, 19),
+    "pr_0.86_d3q19": (dict(eos=1, a=2.0 / 49.0, b=2.0 / 21.0), 0.86, 1.0, 19),
 }
 
 

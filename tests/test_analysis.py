@@ -54,3 +54,27 @@ def test_cylinder_angle_of_synthetic_droplet(theta):
     rho[solid == 1] = 0.0
     th, _ = A.contact_angle_cylinder(rho, solid, c, Rn, RG, RL)
     assert abs(th - theta) < 1.0
+
+
+def test_fit_sphere_exact_points():
+    rng = np.random.default_rng(3)
+    v = rng.normal(size=(200, 3))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    pts = np.array([1.0, -2.0, 0.5]) + 9.0 * v
+    cx, cy, cz, r = A.fit_sphere(pts)
+    assert max(abs(cx - 1.0), abs(cy + 2.0), abs(cz - 0.5), abs(r - 9.0)) < 1e-9
+
+
+@pytest.mark.parametrize("theta", [50.0, 120.0])
+def test_sphere_angle_of_synthetic_droplet(theta):
+    n, Rn, r = 96, 20, 16.0
+    c = (48.0, 48.0, 40.0)
+    Rw = Rn + 0.5
+    d = np.sqrt(r * r + Rw * Rw - 2.0 * r * Rw * np.cos(np.radians(theta)))
+    z, y, x = np.mgrid[0:n, 0:n, 0:n].astype(float)
+    dd = np.sqrt((x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2] - d) ** 2)
+    rho = 0.5 * (RL + RG) - 0.5 * (RL - RG) * np.tanh(2.0 * (dd - r) / 3.0)
+    solid = (((x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2) <= Rn * Rn).astype(np.uint8)
+    rho[solid == 1] = 0.0
+    th, _ = A.contact_angle_sphere(rho, solid, c, Rn, RG, RL)
+    assert abs(th - theta) < 1.0

@@ -11,11 +11,16 @@ readings, not the paper's values); it is held to 10 deg.  FP32 angles
 within 0.5 deg of FP64.  The solid-fluid interaction cases of Fig. 6 are
 not checked: with psi = 0 at solid nodes in Eq. 5 the printed G_w values
 do not reproduce them.
+
+Near 120 deg (Figs. 9-11): the paper finds spurious currents below 0.006
+for the virtual-density schemes, larger with the constant virtual density
+than with the improved one, and fluid density extrema that agree with the
+coexistence densities 6.5 and 0.38.
 """
 import numpy as np
 import pytest
 
-from cases import SIGMA_PR086, lib_params, oracle_params
+from cases import SIGMA_CAL, SIGMA_PR086, lib_params, oracle_params
 from paper_1908_04443_amd import analysis as A
 from paper_1908_04443_amd import inputs as I
 
@@ -34,7 +39,8 @@ CASES = {
 _cache = {}
 
 
-def _angle(O, L, key, precision):
+def _run(O, L, key, precision):
+    """(theta, max |u|, min rho, max rho over the fluid) after STEPS steps."""
     if (key, precision) in _cache:
         return _cache[(key, precision)]
     import torch
@@ -66,8 +72,14 @@ def _angle(O, L, key, precision):
                                        select=lambda x, y: y > CC[1])
     print(f"{key} FP{8 * precision}: theta {th:.2f} (circle fit {fit[0]:.1f} {fit[1]:.1f} "
           f"{fit[2]:.1f}, {fit[3]} points)", flush=True)
-    _cache[(key, precision)] = th
-    return th
+    _cache[(key, precision)] = (th, d["max_u"], d["rho_min"], d["rho_max"], op.rho_g, op.rho_l)
+    print(f"{key} FP{8 * precision}: max|u| {d['max_u']:.3e}, rho {d['rho_min']:.4f} .. "
+          f"{d['rho_max']:.4f}", flush=True)
+    return _cache[(key, precision)]
+
+
+def _angle(O, L, key, precision):
+    return _run(O, L, key, precision)[0]
 
 
 @pytest.mark.parametrize("key", list(CASES))
@@ -82,3 +94,60 @@ def test_cylinder_angle_fp32_within_half_degree(oracle_mod, gpu_lib, key):
     th64 = _angle(oracle_mod, gpu_lib, key, 8)
     th32 = _angle(oracle_mod, gpu_lib, key, 4)
     assert abs(th32 - th64) <= 0.5
+
+
+def test_spurious_currents_near_120deg(oracle_mod, gpu_lib):
+    th_i, u_ivd, *_ = _run(oracle_mod, gpu_lib, "ivd_drho0.5", 8)
+    th_v, u_vd, *_ = _run(oracle_mod, gpu_lib, "vd_1.5", 8)
+    assert u_ivd < 0.006
+    assert u_vd > u_ivd  # the constant virtual density gives the larger currents
+    assert u_vd < 0.0075  # the paper's 0.006 bound, read off its figure, plus 25 %
+
+
+@pytest.mark.parametrize("key", list(CASES))
+def test_fluid_density_extrema_match_coexistence(oracle_mod, gpu_lib, key):
+    _, _, rmin, rmax, rg, rl = _run(oracle_mod, gpu_lib, key, 8)
+    assert abs(rmax / rl - 1.0) < 0.03
+    assert abs(rmin / rg - 1.0) < 0.10
+
+
+# Fig. 14: D3Q19, 200 x 200 x 280 periodic, sphere R = 50 at (100, 100, 100),
+# droplet r = 45 at (100, 100, 180), PR at 0.86 Tc, nu = 0.15.  FP32 (its
+# parity with FP64 and the oracle is tested on smaller boxes); 25000 steps,
+# within 1 deg of the 40000-step angle.  The drho branch reads high, as in
+# 2-D (about 152 deg against the printed 145).
+SPHERE_CASES = {"phi1.2": (1.2, 0.0, 53.0, 3.0), "phi1": (1.0, 0.0, 88.0, 3.0),
+                "drho0.55": (1.0, 0.55, 145.0, 10.0)}
+
+
+@pytest.mark.parametrize("key", list(SPHERE_CASES))
+def test_sphere_angle_fp32_vs_paper(oracle_mod, gpu_lib, key):
+    import torch
+    L = gpu_lib
+    phi, drho, ref, tol = SPHERE_CASES[key]
+    nx, ny, nz, Rs, cs, r0, dc = 200, 200, 280, 50, (100, 100, 100), 45, (100, 100, 180)
+    tau = [1.0] * 19
+    for k in (9, 11, 13, 14, 15):  # the viscous rows: nu = 0.15
+        tau[k] = 0.95
+    case = dict(lattice=19, nx=nx, ny=ny, nz=nz, eos="pr", T_ratio=0.86,
+                sigma=SIGMA_CAL["pr_0.86_d3q19"]["sigma"], tau=tau, precision=4)
+    op = oracle_params(oracle_mod, case)
+    p = lib_params(L, op, case)
+    shape = (nz, ny, nx)
+    solid = I.disk_mask(shape, cs, Rs)
+    rho0 = I.droplet_rho(shape, dc, r0, op.rho_g, op.rho_l, solid=solid)
+    s = L.Solver(p, int(solid.sum()))
+    s.set_geometry(solid)
+    nw = len(s.wall_nodes())
+    s.set_wetting(L.LBM_WET_IVD, 0.0, torch.full((nw,), phi, dtype=s.dtype, device=s.device),
+                  torch.full((nw,), drho, dtype=s.dtype, device=s.device))
+    s.set_fields(rho0.ravel())
+    s.step(25000)
+    rc, d = s.diagnostics()
+    rho = s.get_fields(rho=True, u=False)["rho"].double().cpu().numpy().reshape(shape)
+    s.close()
+    assert rc == 0
+    th, fit = A.contact_angle_sphere(rho, solid, cs, Rs, op.rho_g, op.rho_l,
+                                     select=lambda x, y, z: z > cs[2])
+    print(f"sphere {key}: theta {th:.2f} (printed {ref}), max|u| {d['max_u']:.2e}", flush=True)
+    assert abs(th - ref) < tol
