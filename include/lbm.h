@@ -56,7 +56,7 @@ enum {
 };
 
 enum { LBM_EOS_CS = 0, LBM_EOS_PR = 1 };
-enum { LBM_WET_IVD = 0, LBM_WET_VD = 1, LBM_WET_SFI = 2 };
+enum { LBM_WET_IVD = 0, LBM_WET_VD = 1, LBM_WET_SFI = 2, LBM_WET_GF = 3 };
 
 /* Model parameters, copied at create.
  *  lattice     9 (D2Q9) or 19 (D3Q19)
@@ -166,8 +166,20 @@ int lbm_wall_nodes(lbm_ctx* ctx, int64_t* idx_host, int64_t* count);
  *  LBM_WET_VD   constant virtual density rho_w = scalar on every wall node.
  *  LBM_WET_SFI  solid-fluid interaction (Eq. 8) with G_w = scalar; the
  *               solid carries psi = 0.
+ *  LBM_WET_GF   curved geometric formulation (Sec. III A, Eqs. 11, 13-15),
+ *               D2Q9 single-lattice contexts only: each wall node takes
+ *               the max (theta_a <= 90 deg) or min of the densities at the
+ *               two points D1, D2 where the characteristic lines through it
+ *               (the solid normal of Eq. 13 with the weights of Eq. 14,
+ *               turned by +-(90 deg - theta_a), Eq. 15) first cross a mesh
+ *               line, interpolated linearly between that line's two fluid
+ *               nodes.  theta_a in degrees: scalar for every wall node, or
+ *               phi_dev = device array of count wall entries in the context
+ *               precision (drho_dev ignored).  The stencils are built on the
+ *               host during the call (it copies phi_dev to the host).
  * Errors: LBM_ESTATE (no geometry), LBM_EINVAL (unknown scheme, phi <= 0,
- * VD density outside the range where Eq. 6 is real). */
+ * VD density outside the range where Eq. 6 is real, GF angle outside
+ * (0, 180) or GF on a D3Q19 or multi-case context). */
 int lbm_set_wetting(lbm_ctx* ctx, int32_t scheme, double scalar,
                     const void* phi_dev, const void* drho_dev, double phi0,
                     double drho0);
@@ -278,7 +290,8 @@ int lbm_get_diagnostics_case(lbm_ctx* ctx, int32_t i, lbm_diag* host_out);
  * caller-owned device memory of at least lbm_adjoint_workspace_bytes(ctx,
  * K) bytes.  The context state is not changed.  Gradients through the
  * clamp of the limiter are taken as 1 on the closed interval
- * [rho_g, rho_l] and 0 outside. */
+ * [rho_g, rho_l] and 0 outside.  The geometric formulation has no adjoint
+ * (LBM_EINVAL). */
 size_t lbm_adjoint_workspace_bytes(lbm_ctx* ctx, int64_t K);
 int lbm_step_ckpt(lbm_ctx* ctx, int64_t T, int64_t K, void* ckpt_dev);
 int lbm_adjoint(lbm_ctx* ctx, int32_t seed_kind, const void* seed_dev, int64_t T, int64_t K,

@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _lib = None
 
 EOS_CS, EOS_PR = 0, 1
-IVD, VD, SFI = 0, 1, 2
+IVD, VD, SFI, GF = 0, 1, 2, 3
 OK, EINVAL, EDOMAIN = 0, -1, -3
 
 

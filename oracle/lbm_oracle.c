@@ -163,6 +163,8 @@ static int check_params(const orc_params* p) {
     if (p->lattice != 9 && p->lattice != 19) return ORC_EINVAL;
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) return ORC_EINVAL;
     if (p->lattice == 9 && p->nz != 1) return ORC_EINVAL;
+    if (p->scheme < ORC_IVD || p->scheme > ORC_GF) return ORC_EINVAL;
+    if (p->scheme == ORC_GF && p->lattice != 9) return ORC_EINVAL;  /* 2-D scheme */
     return ORC_OK;
 }
 
@@ -336,6 +338,102 @@ static void work_free(work_t* w) {
     free(w->fpost);
 }
 
+/* ------------------------------------------------------------------------
+ * Curved geometric formulation (Sec. III A), 2-D.  For a wall node P:
+ *   n_s  from Eq. 13 with the 8th-order isotropic weights of Eq. 14 over the
+ *        24 neighbours with |e|^2 = 1, 2, 4, 5, 8 (s = 1 on solid nodes);
+ *   n_1, n_2  n_s rotated by +-(pi/2 - theta_a), Eq. 15;
+ *   D_k  the first crossing of the ray P + t n_k with a mesh line (the
+ *        vertical lines x_P +- 1 or the horizontal lines y_P +- 1, whichever
+ *        the ray meets first); rho(D_k) interpolates linearly between the two
+ *        lattice nodes of that line segment, using only fluid nodes (one
+ *        fluid node: its density; none: D_k is void; a crossing that falls
+ *        on a lattice node is that node alone);
+ *   rho_P = max(rho_D1, rho_D2) for theta_a <= 90 deg, min otherwise, Eq. 11
+ *        (one void point: the other; both void: the neighbour mean of Eq. 17).
+ * The paper leaves the location of D_1, D_2 to its Ref. [26]; this is the
+ * reading taken here. */
+static int64_t node_at(const orc_params* p, int64_t n, int dx, int dy) {
+    int32_t e[3] = {dx, dy, 0};
+    return nbr(p, n, e);
+}
+
+static real gf_point(const orc_params* p, const uint8_t* solid, const real* rho,
+                     int64_t b, double vx, double vy, int* ok) {
+    double tx = fabs(vx) > 1e-12 ? 1.0 / fabs(vx) : 1e300;
+    double ty = fabs(vy) > 1e-12 ? 1.0 / fabs(vy) : 1e300;
+    int64_t na, nb;
+    double t;
+    if (tx <= ty) {
+        /* vertical mesh line x_P + sign(vx); crossing at y_P + tx vy */
+        int sx = vx > 0 ? 1 : -1;
+        double yc = tx * vy;
+        int y0 = (int)floor(yc);
+        t = yc - y0;
+        na = node_at(p, b, sx, y0);
+        nb = node_at(p, b, sx, y0 + 1);
+    } else {
+        int sy = vy > 0 ? 1 : -1;
+        double xc = ty * vx;
+        int x0 = (int)floor(xc);
+        t = xc - x0;
+        na = node_at(p, b, x0, sy);
+        nb = node_at(p, b, x0 + 1, sy);
+    }
+    int fa = !solid[na], fb = !solid[nb];
+    if (t == 0.0) fb = 0;  /* the crossing is the lattice node a itself */
+    *ok = fa || fb;
+    if (fa && fb) return (1.0 - t) * rho[na] + t * rho[nb];
+    if (fa) return rho[na];
+    if (fb) return rho[nb];
+    return 0.0;
+}
+
+static real gf_density(const orc_params* p, const lat_t* L, const uint8_t* solid,
+                       const real* rho, int64_t b, double theta_deg) {
+    static const int off[24][2] = {
+        {1, 0}, {-1, 0}, {0, 1}, {0, -1}, {1, 1}, {-1, 1}, {-1, -1}, {1, -1},
+        {2, 0}, {-2, 0}, {0, 2}, {0, -2}, {2, 1}, {1, 2}, {-1, 2}, {-2, 1},
+        {-2, -1}, {-1, -2}, {1, -2}, {2, -1}, {2, 2}, {-2, 2}, {-2, -2}, {2, -2}};
+    double sx = 0.0, sy = 0.0;
+    for (int i = 0; i < 24; ++i) {
+        int e2 = off[i][0] * off[i][0] + off[i][1] * off[i][1];
+        double om = e2 == 1 ? 4.0 / 21.0 : e2 == 2 ? 4.0 / 45.0 : e2 == 4 ? 1.0 / 60.0
+                  : e2 == 5 ? 2.0 / 315.0 : 1.0 / 5040.0;
+        if (solid[node_at(p, b, off[i][0], off[i][1])]) {
+            sx += om * off[i][0];
+            sy += om * off[i][1];
+        }
+    }
+    double norm = sqrt(sx * sx + sy * sy);
+    /* Eq. 17, the standard case, when no direction can be formed */
+    real num = 0.0;
+    double den = 0.0;
+    for (int a = 1; a < L->Q; ++a) {
+        int64_t y = nbr(p, b, &L->e[3 * a]);
+        if (!solid[y]) {
+            num += L->w[a] * rho[y];
+            den += L->w[a];
+        }
+    }
+    real rave = num / den;
+    if (norm == 0.0) return rave;
+    double nx = -sx / norm, ny = -sy / norm;
+    const double pi = 3.14159265358979323846;
+    double th = theta_deg * (pi / 180.0), tp = 0.5 * pi - th;
+    double c = cos(tp), s = sin(tp);
+    double n1x = nx * c - ny * s, n1y = nx * s + ny * c;
+    double n2x = nx * c + ny * s, n2y = -nx * s + ny * c;
+    int ok1, ok2;
+    real r1 = gf_point(p, solid, rho, b, n1x, n1y, &ok1);
+    real r2 = gf_point(p, solid, rho, b, n2x, n2y, &ok2);
+    if (!ok1 && !ok2) return rave;
+    if (!ok1) return r2;
+    if (!ok2) return r1;
+    if (theta_deg <= 90.0) return RE(r1) >= RE(r2) ? r1 : r2;
+    return RE(r1) <= RE(r2) ? r1 : r2;
+}
+
 /* Phases 1-5 of the step: density, psi, wall virtual density, force and
  * velocity at time t from the post-streaming populations f. */
 static int macro_phases(const orc_params* p, const lat_t* L, const geom_t* g,
@@ -385,6 +483,9 @@ static int macro_phases(const orc_params* p, const lat_t* L, const geom_t* g,
             if (RE(rw) < p->rho_g) rw = p->rho_g;
             w->rho[b] = rw;
             if (psi_of(p, rw, &w->psi[b]) != ORC_OK) return ORC_EDOMAIN;
+        } else if (p->scheme == ORC_GF) {
+            w->rho[b] = gf_density(p, L, solid, w->rho, b, RE(phi[k]));
+            if (psi_of(p, w->rho[b], &w->psi[b]) != ORC_OK) return ORC_EDOMAIN;
         } else if (p->scheme == ORC_VD) {
             /* original scheme: one constant virtual density for the solid */
             w->rho[b] = p->rho_w;

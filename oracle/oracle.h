@@ -25,7 +25,11 @@ extern "C" {
 #endif
 
 enum { ORC_EOS_CS = 0, ORC_EOS_PR = 1 };
-enum { ORC_IVD = 0, ORC_VD = 1, ORC_SFI = 2 };
+/* wetting schemes: improved virtual density (Eqs. 16-17), constant virtual
+ * density, solid-fluid interaction (Eq. 8), curved geometric formulation
+ * (Eqs. 11, 13-15; 2-D only; the per-wall prescribed angle theta_a in
+ * degrees is passed in the phi array) */
+enum { ORC_IVD = 0, ORC_VD = 1, ORC_SFI = 2, ORC_GF = 3 };
 enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_EDOMAIN = -3 };
 
 typedef struct {
@@ -37,7 +41,7 @@ typedef struct {
     double G;               /* interaction strength of Eq. 5 (-1 in the paper) */
     double sigma;           /* thermodynamic-consistency constant of Eq. 7 */
     double body_force[3];   /* constant body force added to F */
-    int32_t scheme;         /* ORC_IVD, ORC_VD, ORC_SFI */
+    int32_t scheme;         /* ORC_IVD, ORC_VD, ORC_SFI, ORC_GF */
     double rho_w;           /* VD constant virtual density */
     double G_w;             /* SFI adhesion strength (Eq. 8) */
     double rho_g, rho_l;    /* limiter bounds of the improved scheme */

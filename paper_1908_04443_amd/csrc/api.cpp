@@ -102,6 +102,7 @@ static Fields<real> make_fields(const lbm_ctx* c, int src) {
     F.drho = (const real*)c->drho;
     F.flag = c->flag;
     F.rho = (real*)c->rho;
+    F.gfcode = c->gfcode;
     return F;
 }
 
@@ -153,8 +154,12 @@ static size_t layout(const lbm_params& p, int64_t nwm, lbm_ctx* c) {
     int32_t* tww = cv.take<int32_t>(twcap);
     void* twphi = cv.take<char>(twcap * s);
     void* twdrho = cv.take<char>(twcap * s);
+    int32_t* twc = cv.take<int32_t>(twcap);
+    int32_t* gfc = cv.take<int32_t>(nw);
     if (c) {
         c->rho = rho;
+        c->tw_code = twc;
+        c->gfcode = gfc;
         c->tw_pack = twp;
         c->tw_widx = tww;
         c->tw_phi = twphi;
@@ -228,6 +233,7 @@ static hipError_t launch_one(lbm_ctx* c, const Coef<real>& C, int src, hipStream
             B.tw_phi = (const real*)c->tw_phi;
             B.tw_drho = (const real*)c->tw_drho;
             B.tw_stride = c->tw_stride;
+            B.tw_code = c->tw_code;
         }
         return launch_step2d_batch<real>(C, B, c->ntiles, c->variant, s);
     }
@@ -237,6 +243,7 @@ static hipError_t launch_one(lbm_ctx* c, const Coef<real>& C, int src, hipStream
         F.tw_phi = (const real*)c->tw_phi;
         F.tw_drho = (const real*)c->tw_drho;
         F.tw_stride = c->tw_stride;
+        F.tw_code = c->tw_code;
     }
     FieldOut<real> O{nullptr, nullptr, nullptr};
     return (c->p.lattice == 9) ? launch_step2d<real>(C, F, O, MODE_STEP, c->variant, s)
@@ -337,6 +344,8 @@ static int upload_wall_lists(lbm_ctx* c, const std::vector<ListTile>& tiles, int
     LBM_HIP(launch_gather_wall<real>(c->tw_widx, (const real*)c->phi, (const real*)c->drho,
                                      (real*)c->tw_phi, (real*)c->tw_drho, nt * stride,
                                      c->stream));
+    if (c->scheme == LBM_WET_GF)
+        LBM_HIP(launch_gather_code(c->tw_widx, c->gfcode, c->tw_code, nt * stride, c->stream));
     LBM_HIP(hipStreamSynchronize(c->stream));  // the host vectors go out of scope
     c->tw_stride = stride;
     return LBM_OK;
@@ -344,7 +353,7 @@ static int upload_wall_lists(lbm_ctx* c, const std::vector<ListTile>& tiles, int
 
 template <typename real>
 static int ensure_wall_lists(lbm_ctx* c) {
-    const bool want = c->p.lattice == 9 && c->scheme == LBM_WET_IVD &&
+    const bool want = c->p.lattice == 9 && (c->scheme == LBM_WET_IVD || c->scheme == LBM_WET_GF) &&
                       c->variant < tile2d_variants<real>() && (c->is_batch || c->have_geom);
     if (!want) {
         c->tw_stride = 0;
@@ -423,6 +432,7 @@ static Fields<real> case_fields(const lbm_ctx* c, const lbm_case& k) {
     F.drho = (const real*)c->drho + k.wall_off;
     F.flag = c->flag;
     F.rho = (real*)c->rho;
+    F.gfcode = c->gfcode;
     return F;
 }
 
@@ -456,6 +466,41 @@ static int fill_wetting(lbm_ctx* c, const void* phi_dev, const void* drho_dev, d
         for (int64_t i = 0; i < nw; ++i)
             if (!(h[i] > 0)) return fail(LBM_EINVAL, "phi must be positive on every wall node");
     }
+    return LBM_OK;
+}
+
+// Geometric formulation: prescribed angles (per wall node from the device,
+// or one value) -> stencil codes and interpolation weights (host), stored
+// in gfcode and in the phi/drho arrays of the context.
+template <typename real>
+static int fill_gf(lbm_ctx* c, const void* theta_dev, double theta0) {
+    const int64_t nw = (int64_t)c->geom.walls.size();
+    std::vector<double> th(nw, theta0);
+    if (theta_dev && nw > 0) {
+        std::vector<real> h(nw);
+        LBM_HIP(hipMemcpyAsync(h.data(), theta_dev, (size_t)nw * sizeof(real),
+                               hipMemcpyDeviceToHost, c->stream));
+        LBM_HIP(hipStreamSynchronize(c->stream));
+        for (int64_t i = 0; i < nw; ++i) th[i] = (double)h[i];
+    }
+    for (int64_t i = 0; i < nw; ++i)
+        if (!(th[i] > 0.0 && th[i] < 180.0))
+            return fail(LBM_EINVAL, "geometric formulation: angles must lie in (0, 180) degrees");
+    if (nw == 0) return LBM_OK;
+    std::vector<int32_t> code;
+    std::vector<double> t;
+    build_gf_stencils(c->p, c->geom, th.data(), code, t);
+    std::vector<real> t0(nw), t1(nw);
+    for (int64_t i = 0; i < nw; ++i) {
+        t0[i] = (real)t[2 * i];
+        t1[i] = (real)t[2 * i + 1];
+    }
+    LBM_HIP(hipMemcpyAsync(c->gfcode, code.data(), (size_t)nw * 4, hipMemcpyHostToDevice, c->stream));
+    LBM_HIP(hipMemcpyAsync(c->phi, t0.data(), (size_t)nw * sizeof(real), hipMemcpyHostToDevice,
+                           c->stream));
+    LBM_HIP(hipMemcpyAsync(c->drho, t1.data(), (size_t)nw * sizeof(real), hipMemcpyHostToDevice,
+                           c->stream));
+    LBM_HIP(hipStreamSynchronize(c->stream));  // the host vectors go out of scope
     return LBM_OK;
 }
 
@@ -527,6 +572,7 @@ static size_t layout_batch(const lbm_params& p, int ncases, const int32_t* nx, c
     int32_t* tww = cv.take<int32_t>(tiles_max * 256);
     void* twphi = cv.take<char>(tiles_max * 256 * s);
     void* twdrho = cv.take<char>(tiles_max * 256 * s);
+    int32_t* twc = cv.take<int32_t>(tiles_max * 256);
     int32_t* flag = cv.take<int32_t>(4);
     double* part = cv.take<double>(5 * (size_t)max_parts);
     double* dout = cv.take<double>(8);
@@ -544,6 +590,7 @@ static size_t layout_batch(const lbm_params& p, int ncases, const int32_t* nx, c
         c->tw_widx = tww;
         c->tw_phi = twphi;
         c->tw_drho = twdrho;
+        c->tw_code = twc;
         c->tw_cap = tiles_max * 256;
         c->flag = flag;
         c->part = part;
@@ -846,6 +893,11 @@ int lbm_set_wetting(lbm_ctx* c, int32_t scheme, double scalar, const void* phi_d
             return fail(LBM_EINVAL, "virtual density outside the range where psi is real");
     } else if (scheme == LBM_WET_SFI) {
         if (!std::isfinite(scalar)) return fail(LBM_EINVAL, "G_w must be finite");
+    } else if (scheme == LBM_WET_GF) {
+        if (c->is_batch || c->p.lattice != 9)
+            return fail(LBM_EINVAL, "the geometric formulation is for D2Q9 single-lattice contexts");
+        int rc = c->prec == 4 ? fill_gf<float>(c, phi_dev, scalar) : fill_gf<double>(c, phi_dev, scalar);
+        if (rc != LBM_OK) return rc;
     } else {
         return fail(LBM_EINVAL, "unknown wetting scheme");
     }
@@ -1304,6 +1356,9 @@ int lbm_adjoint(lbm_ctx* c, int32_t seed_kind, const void* seed_dev, int64_t T, 
     if (c->is_batch || c->p.lattice != 9)
         return fail(LBM_EINVAL, "the adjoint is implemented for single D2Q9 lattices");
     if (seed_kind != 0 && seed_kind != 1) return fail(LBM_EINVAL, "seed_kind must be 0 or 1");
+    if (c->scheme == LBM_WET_GF)
+        return fail(LBM_EINVAL, "no adjoint of the geometric formulation (its max/min and "
+                                "interpolation stencils have no parameters to differentiate)");
     if (T < 1 || K < 1) return fail(LBM_EINVAL, "need T >= 1 and K >= 1");
     if (!c->have_geom) return fail(LBM_ESTATE, "no geometry set");
     if (c->domain_error) return fail(LBM_EDOMAIN, "a previous step left the psi domain");

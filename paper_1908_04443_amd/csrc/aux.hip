@@ -85,7 +85,22 @@ __global__ void k_gather_wall(const int32_t* __restrict__ widx, const real* __re
     odrho[i] = k >= 0 ? drho[k] : real(0);
 }
 
+__global__ void k_gather_code(const int32_t* __restrict__ widx, const int32_t* __restrict__ code,
+                              int32_t* __restrict__ out, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t k = widx[i];
+    out[i] = k >= 0 ? code[k] : 0;
+}
+
 static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+hipError_t launch_gather_code(const int32_t* widx, const int32_t* code, int32_t* out, int64_t n,
+                              hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_code, dim3(nblk(n, 256)), dim3(256), 0, s, widx, code, out, n);
+    return hipGetLastError();
+}
 
 template <typename real>
 hipError_t launch_gather_wall(const int32_t* widx, const real* phi, const real* drho, real* ophi,

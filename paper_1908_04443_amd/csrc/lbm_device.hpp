@@ -20,7 +20,7 @@ namespace lbm {
 
 // node classes stored per node (one byte)
 enum : uint8_t { CLS_FLUID = 0, CLS_SOLID = 1, CLS_WALL = 3 };
-enum { WET_IVD = 0, WET_VD = 1, WET_SFI = 2 };
+enum { WET_IVD = 0, WET_VD = 1, WET_SFI = 2, WET_GF = 3 };
 enum { EOS_CS = 0, EOS_PR = 1 };
 
 // ------------------------------------------------------------------ D2Q9
@@ -131,6 +131,10 @@ struct Fields {
     const real* tw_phi = nullptr;
     const real* tw_drho = nullptr;
     int tw_stride = 0;
+    // geometric formulation: stencil code per wall node (phi, drho then hold
+    // the two interpolation weights) and per wall-list entry
+    const int32_t* gfcode = nullptr;
+    const int32_t* tw_code = nullptr;
 };
 
 // Workgroups are handed to the 8 XCDs of the chip round-robin by linear id.

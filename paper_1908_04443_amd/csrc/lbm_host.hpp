@@ -45,6 +45,13 @@ struct Geometry {
     int64_t n_fluid = 0;
 };
 int build_geometry(const lbm_params& p, const uint8_t* solid, Geometry& g);
+// Geometric-formulation stencils of every wall node (D2Q9): code packs, for
+// the two characteristic points k = 0, 1, the 3x3 neighbour index (dx+1) +
+// 3 (dy+1) of the two mesh-line nodes a, b (4 bits each, at bit 10 k) and
+// whether each is fluid (bits 8, 9 of the k field); bit 20: take the min
+// (theta_a > 90 deg) instead of the max; t[2 w + k] the weight of b.
+void build_gf_stencils(const lbm_params& p, const Geometry& g, const double* theta_deg,
+                       std::vector<int32_t>& code, std::vector<double>& t);
 
 // ---- workspace carving
 struct Carver {
@@ -94,8 +101,10 @@ struct lbm_ctx {
     double* diag_out = nullptr;
     void* rho = nullptr;  // node densities written by the density pass (sweep kernels)
     int nparts = 0;
+    int32_t* gfcode = nullptr;  // geometric-formulation stencil code per wall node
     // per-tile wall lists of the D2Q9 tile step (see Fields::tw_pack)
     int32_t* tw_pack = nullptr;
+    int32_t* tw_code = nullptr;  // gfcode of each entry
     int32_t* tw_widx = nullptr;  // wall-list index of each entry, -1 when empty
     void* tw_phi = nullptr;
     void* tw_drho = nullptr;

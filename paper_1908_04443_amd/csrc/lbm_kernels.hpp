@@ -49,6 +49,7 @@ struct BatchArgs {
     const real* tw_phi = nullptr;
     const real* tw_drho = nullptr;
     int tw_stride = 0;
+    const int32_t* tw_code = nullptr;
 };
 
 // wave64 butterfly reduction followed by a fixed-order pass over the waves of
@@ -163,6 +164,8 @@ hipError_t launch_mask_solid(int Q, const uint8_t* cls, real* f, int64_t N, hipS
 template <typename real>
 hipError_t launch_fill(real* p, real v, int64_t n, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+hipError_t launch_gather_code(const int32_t* widx, const int32_t* code, int32_t* out, int64_t n,
+                              hipStream_t s);
 template <typename real>
 hipError_t launch_gather_wall(const int32_t* widx, const real* phi, const real* drho, real* ophi,
                               real* odrho, int64_t n, hipStream_t s);

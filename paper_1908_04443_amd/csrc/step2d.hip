@@ -176,6 +176,7 @@ __global__ __launch_bounds__(NT) void k_step_d2q9_batch(Coef<real> C, BatchArgs<
     Fd.tw_phi = B.tw_phi;
     Fd.tw_drho = B.tw_drho;
     Fd.tw_stride = B.tw_stride;
+    Fd.tw_code = B.tw_code;
     FieldOut<real> none{nullptr, nullptr, nullptr};
     d2q9_tile<real, TX, TY, NT, MODE_STEP, BUF>(C, Fd, none, cd.nx, cd.ny, t.x0, t.y0, bid, bid);
 }
@@ -255,6 +256,8 @@ hipError_t launch_step2d(const Coef<real>& C, const Fields<real>& F, const Field
         else launch_v<real, 0, MODE_FIELDS, false>(C, F, O, s);
         return hipGetLastError();
     }
+    // the sweep kernels have no geometric formulation: its steps run tiled
+    if (variant >= Variants2D<real>::count && C.scheme == WET_GF) variant = Variants2D<real>::preferred;
     if (variant >= Variants2D<real>::count)
         return launch_step2d_march<real>(C, F, O, variant - Variants2D<real>::count, s);
     if (variant < 0) return hipErrorInvalidValue;

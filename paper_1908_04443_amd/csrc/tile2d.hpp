@@ -42,6 +42,57 @@ __device__ __forceinline__ void ring_pos(int j, int& lx, int& ly) {
     }
 }
 
+// w-weighted mean density of the fluid neighbours of LDS position p (Eq. 17)
+template <typename real, int LX>
+__device__ __forceinline__ real fluid_mean(const uint8_t* cls, const real* rho, int p) {
+    using L = D2Q9;
+    real num = real(0), den = real(0);
+    bool first = true;
+#pragma unroll
+    for (int a = 1; a < 9; ++a) {
+        const int q = p + L::ex[a] + L::ey[a] * LX;
+        if (cls[q] == CLS_FLUID) {
+            const real w = real(L::w12[a]) * real(1.0 / 12.0);
+            num = first ? w * rho[q] : num + w * rho[q];
+            den = first ? w : den + w;
+            first = false;
+        }
+    }
+    return fdiv(num, den);
+}
+
+// Geometric formulation (Eq. 11) at wall position p from its stencil code
+// (see build_gf_stencils): the density at each characteristic point
+// interpolates its two mesh-line nodes (weight t_k on the second), then the
+// max or min of the two points; a void point drops out, two void points
+// give the neighbour mean.
+template <typename real, int LX>
+__device__ __forceinline__ real gf_density(const uint8_t* cls, const real* rho, int p,
+                                           int32_t code, real t0, real t1) {
+    real r[2];
+    bool ok[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int f = (code >> (10 * k)) & 0x3FF;
+        const int ia = f & 15, ib = (f >> 4) & 15;
+        const bool fa = (f >> 8) & 1, fb = (f >> 9) & 1;
+        const int qa = p + (ia % 3 - 1) + (ia / 3 - 1) * LX;
+        const int qb = p + (ib % 3 - 1) + (ib / 3 - 1) * LX;
+        const real t = k == 0 ? t0 : t1;
+        ok[k] = fa || fb;
+        r[k] = (fa && fb) ? (real(1) - t) * rho[qa] + t * rho[qb]
+               : fa       ? rho[qa]
+               : fb       ? rho[qb]
+                          : real(0);
+    }
+    if (!ok[0] && !ok[1]) return fluid_mean<real, LX>(cls, rho, p);
+    if (!ok[0]) return r[1];
+    if (!ok[1]) return r[0];
+    const bool take_min = (code >> 20) & 1;
+    if (take_min) return r[0] <= r[1] ? r[0] : r[1];
+    return r[0] >= r[1] ? r[0] : r[1];
+}
+
 template <typename real, int TX, int TY, int NT, bool BUF>
 __device__ __forceinline__ void d2q9_prologue(const Coef<real>& C, const Fields<real>& Fd,
                                               const PopIO<real, BUF>& io, const int nx,
@@ -75,9 +126,10 @@ __device__ __forceinline__ void d2q9_prologue(const Coef<real>& C, const Fields<
     // Per-tile wall list (improved virtual density): the first wave loads
     // the first 64 entries with the other loads of this phase; entries
     // beyond 64 (rare) follow after the barrier.
-    const bool wl_on = C.scheme == WET_IVD && Fd.tw_pack != nullptr;
+    const bool wl_on = (C.scheme == WET_IVD || C.scheme == WET_GF) && Fd.tw_pack != nullptr;
     uint32_t wl_e0 = 0;
     int wl_pos = -1;
+    int32_t wl_code = 0;
     real wl_phi = real(0), wl_drho = real(0);
     if (wl_on) {
         wl_e0 = (uint32_t)list_tile * (uint32_t)Fd.tw_stride;
@@ -85,6 +137,7 @@ __device__ __forceinline__ void d2q9_prologue(const Coef<real>& C, const Fields<
             const int w = Fd.tw_pack[wl_e0 + tid];
             wl_phi = Fd.tw_phi[wl_e0 + tid];
             wl_drho = Fd.tw_drho[wl_e0 + tid];
+            if (C.scheme == WET_GF) wl_code = Fd.tw_code[wl_e0 + tid];
             if (tid < (w >> 16)) wl_pos = w & 0xFFFF;
             if (tid == 0) S.wl_count = w >> 16;
         }
@@ -148,6 +201,7 @@ __device__ __forceinline__ void d2q9_prologue(const Coef<real>& C, const Fields<
         wl_pos = Fd.tw_pack[wl_e0 + tid] & 0xFFFF;
         wl_phi = Fd.tw_phi[wl_e0 + tid];
         wl_drho = Fd.tw_drho[wl_e0 + tid];
+        if (C.scheme == WET_GF) wl_code = Fd.tw_code[wl_e0 + tid];
     }
 
     // psi on tile + 1 halo; wall nodes first get their virtual density
@@ -183,6 +237,12 @@ __device__ __forceinline__ void d2q9_prologue(const Coef<real>& C, const Fields<
                 rw = rw < C.rho_g ? C.rho_g : rw;
                 S.rho[p] = rw;
                 ps = psi_of(C, rw, bad);
+            } else if (C.scheme == WET_GF) {
+                const int kw = Fd.widx[S.row[ly] + S.col[lx]];
+                const real rw = gf_density<real, LX>(S.cls, S.rho, p, Fd.gfcode[kw], Fd.phi[kw],
+                                                     Fd.drho[kw]);
+                S.rho[p] = rw;
+                ps = psi_of(C, rw, bad);
             } else if (C.scheme == WET_VD) {
                 S.rho[p] = C.rho_w;
                 ps = C.psi_w;
@@ -192,7 +252,11 @@ __device__ __forceinline__ void d2q9_prologue(const Coef<real>& C, const Fields<
         }
         S.psi[p] = ps;
     }
-    if (wl_pos >= 0) {
+    if (wl_pos >= 0 && C.scheme == WET_GF) {
+        const real rw = gf_density<real, LX>(S.cls, S.rho, wl_pos, wl_code, wl_phi, wl_drho);
+        S.rho[wl_pos] = rw;
+        S.psi[wl_pos] = psi_of(C, rw, bad);
+    } else if (wl_pos >= 0) {
         // Eq. 17 over the fluid neighbours, Eq. 16 and the limiter
         const int p = wl_pos;
         real num = real(0), den = real(0);

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDOMAIN, LBM_ESTATE, LBM_EDEVICE = 0, -1, -2, -3, -4, -5
 LBM_EOS_CS, LBM_EOS_PR = 0, 1
-LBM_WET_IVD, LBM_WET_VD, LBM_WET_SFI = 0, 1, 2
+LBM_WET_IVD, LBM_WET_VD, LBM_WET_SFI, LBM_WET_GF = 0, 1, 2, 3
 
 
 class lbm_params(C.Structure):

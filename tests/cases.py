@@ -12,7 +12,7 @@ import numpy as np
 
 from paper_1908_04443_amd import inputs as I
 
-SCHEMES = {"ivd": 0, "vd": 1, "sfi": 2}
+SCHEMES = {"ivd": 0, "vd": 1, "sfi": 2, "gf": 3}
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 # flat-slab calibration of Eq. 7's sigma (tests/golden/calibrate_sigma.py)
 SIGMA_CAL = json.load(open(os.path.join(GOLDEN, "sigma_calibration.json")))
@@ -125,7 +125,8 @@ def run_gpu(L, setup, nsteps, precision=None, n_wall_max=None, want_f=False, var
     phi = torch.as_tensor(setup.phi_field.ravel()[walls], dtype=dt, device=s.device)
     drho = torch.as_tensor(setup.drho_field.ravel()[walls], dtype=dt, device=s.device)
     sch = SCHEMES[case.get("scheme", "ivd")]
-    scalar = case.get("rho_w", 0.0) if sch == 1 else case.get("G_w", 0.0)
+    scalar = {1: case.get("rho_w", 0.0), 2: case.get("G_w", 0.0),
+              3: case.get("phi", 90.0)}.get(sch, 0.0)  # GF: phi carries theta_a (deg)
     s.set_wetting(sch, scalar, phi if nw else None, drho if nw else None)
     s.set_fields(setup.rho0.ravel())
     if variant is not None:

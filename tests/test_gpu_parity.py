@@ -186,3 +186,56 @@ def test_autotune_restores_state(oracle_mod, gpu_lib):
     assert sol.variant == best
     import torch
     assert torch.equal(before["f"], after["f"])
+
+
+def _gf_case(precision):
+    rng = np.random.default_rng(9)
+    return dict(C0, scheme="gf", precision=precision,
+                phi_field=lambda solid: 40.0 + 100.0 * rng.random(solid.shape))
+
+
+@pytest.mark.parametrize("variant", [None, 0, 1])
+def test_gf_fp64_vs_oracle(oracle_mod, gpu_lib, variant):
+    """Geometric formulation (per-wall prescribed angles 40..140 deg on the
+    cylinder): FP64 equal to the oracle, through the wall lists (default and
+    variant 0) and through the per-wall lookup (variant 1)."""
+    s = Setup(oracle_mod, _gf_case(8))
+    res = run_gpu(gpu_lib, s, 300, variant=variant)
+    _compare(oracle_mod, s, res, 300, 1e-12, 1e-12)
+
+
+def test_gf_fp32_vs_oracle(oracle_mod, gpu_lib):
+    s = Setup(oracle_mod, _gf_case(4))
+    res = run_gpu(gpu_lib, s, 1000)
+    _compare(oracle_mod, s, res, 1000, 1e-4, 1e-3, rel=True)
+
+
+def test_gf_on_a_sweep_variant_runs_tiled(oracle_mod, gpu_lib):
+    s = Setup(oracle_mod, _gf_case(8))
+    nv = _nvariants(9, 8)
+    res = run_gpu(gpu_lib, s, 100, variant=nv - 1)  # a y-sweep variant
+    _compare(oracle_mod, s, res, 100, 1e-12, 1e-12)
+
+
+def test_gf_rejected_where_undefined(oracle_mod, gpu_lib):
+    """No geometric formulation in 3-D, and no adjoint of it."""
+    import torch
+    L = gpu_lib
+    p3 = L.make_params(lattice=19, precision=8, nx=16, ny=16, nz=16, T_ratio=0.75, sigma=0.1)
+    s3 = L.Solver(p3, 1024)
+    solid = np.zeros((16, 16, 16), np.uint8)
+    solid[0:3] = 1
+    s3.set_geometry(solid)
+    with pytest.raises(L.LBMError):
+        s3.set_wetting(L.LBM_WET_GF, 60.0, None, None)
+    s = Setup(oracle_mod, _gf_case(8))
+    res = run_gpu(gpu_lib, s, 0)
+    sol = res["solver"]
+    with pytest.raises(L.LBMError):
+        sol.set_wetting(L.LBM_WET_GF, 0.0, None, None)  # angle outside (0, 180)
+    T, K = 4, 2
+    ck = sol.ckpt_buffer(T, K)
+    sol.step_ckpt(T, K, ck)
+    seed = torch.zeros(sol.N, dtype=sol.dtype, device=sol.device)
+    with pytest.raises(L.LBMError):
+        sol.adjoint(seed, T, K, ck)

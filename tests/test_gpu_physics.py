@@ -5,8 +5,8 @@ bounce-back.  The GPU FP64 path equals the CPU oracle to 1e-12 on rho, so
 these runs stand for the oracle at a size it cannot finish in a test.
 
 Bars: within 3 deg of the angles printed with Figs. 4 and 5, except the
-drho = 0.5 case of Fig. 5(c), printed as about 125 deg, which this build
-measures near 134 deg (its non-viscous relaxation times and sigma are
+drho = 0.5 case of Fig. 5(c), printed as about 125 deg, which is
+measured near 134 deg (its non-viscous relaxation times and sigma are
 readings, not the paper's values); it is held to 10 deg.  FP32 angles
 within 0.5 deg of FP64.  The solid-fluid interaction cases of Fig. 6 are
 not checked: with psi = 0 at solid nodes in Eq. 5 the printed G_w values
@@ -36,6 +36,7 @@ CASES = {
     "vd_3.25": ("vd", dict(rho_w=3.25), 65.0, 3.0),
     "vd_1.5": ("vd", dict(rho_w=1.5), 121.0, 3.0),
 }
+GF_CASES = {"gf_60": (60.0, 58.0), "gf_90": (90.0, 88.0), "gf_120": (120.0, 121.0)}
 _cache = {}
 
 
@@ -44,7 +45,10 @@ def _run(O, L, key, precision):
     if (key, precision) in _cache:
         return _cache[(key, precision)]
     import torch
-    sch, par, _, _ = CASES[key]
+    if key in GF_CASES:
+        sch, par = "gf", dict(theta=GF_CASES[key][0])
+    else:
+        sch, par, _, _ = CASES[key]
     tau = [1.0] * 9
     tau[7] = tau[8] = 0.95
     case = dict(nx=NX, ny=NY, eos="pr", T_ratio=0.86, sigma=SIGMA_PR086, tau=tau,
@@ -56,7 +60,9 @@ def _run(O, L, key, precision):
     s = L.Solver(p, int(solid.sum()))
     s.set_geometry(solid)
     nw = len(s.wall_nodes())
-    if sch == "ivd":
+    if sch == "gf":
+        s.set_wetting(L.LBM_WET_GF, par["theta"], None, None)
+    elif sch == "ivd":
         s.set_wetting(L.LBM_WET_IVD, 0.0,
                       torch.full((nw,), par["phi"], dtype=s.dtype, device=s.device),
                       torch.full((nw,), par["drho"], dtype=s.dtype, device=s.device))
@@ -151,3 +157,16 @@ def test_sphere_angle_fp32_vs_paper(oracle_mod, gpu_lib, key):
                                      select=lambda x, y, z: z > cs[2])
     print(f"sphere {key}: theta {th:.2f} (printed {ref}), max|u| {d['max_u']:.2e}", flush=True)
     assert abs(th - ref) < tol
+
+
+@pytest.mark.parametrize("key", list(GF_CASES))
+def test_cylinder_angle_geometric_formulation_vs_paper(oracle_mod, gpu_lib, key):
+    """Fig. 8: the curved geometric formulation with theta_a = 60, 90, 120
+    deg; the paper measures about 58, 88 and 121 deg and attributes the
+    difference from theta_a to its interpolation.  The location of the
+    characteristic points is a reading here (its reference is absent), so
+    the bars are 3 deg from theta_a and 5 deg from the printed angle."""
+    th = _angle(oracle_mod, gpu_lib, key, 8)
+    theta_a, printed = GF_CASES[key]
+    assert abs(th - theta_a) < 3.0
+    assert abs(th - printed) < 5.0
