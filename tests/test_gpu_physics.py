@@ -78,7 +78,8 @@ def _run(O, L, key, precision):
                                        select=lambda x, y: y > CC[1])
     print(f"{key} FP{8 * precision}: theta {th:.2f} (circle fit {fit[0]:.1f} {fit[1]:.1f} "
           f"{fit[2]:.1f}, {fit[3]} points)", flush=True)
-    _cache[(key, precision)] = (th, d["max_u"], d["rho_min"], d["rho_max"], op.rho_g, op.rho_l)
+    _cache[(key, precision)] = (th, d["max_u"], d["rho_min"], d["rho_max"], op.rho_g, op.rho_l,
+                                rho[:, NX // 2].copy())
     print(f"{key} FP{8 * precision}: max|u| {d['max_u']:.3e}, rho {d['rho_min']:.4f} .. "
           f"{d['rho_max']:.4f}", flush=True)
     return _cache[(key, precision)]
@@ -229,3 +230,35 @@ def test_droplet_impact_schemes(oracle_mod, gpu_lib):
         d_vd = np.abs(fields[("vd", t)] - fields[("gf", t)])[fluid].mean()
         print(f"t = {t}: mean |rho - rho_GF|  IVD {d_ivd:.4f}  VD {d_vd:.4f}")
         assert d_ivd < 0.2 * d_vd
+
+
+def _layer(profile, start, step, bulk, tol):
+    """Nodes from `start` outward (step +-1) whose density differs from the
+    bulk value by more than tol * bulk: the thickness of a wall layer."""
+    n, y = 0, start
+    while abs(profile[y] - bulk) > tol * bulk and n < 40:
+        n += 1
+        y += step
+    return n
+
+
+def test_mass_transfer_layer_profiles(oracle_mod, gpu_lib):
+    """Fig. 7: along x = N_x / 2 the constant virtual density leaves a layer
+    of about four lattices next to the cylinder (solid for y in [60, 200])
+    whose density departs from the surrounding phase; the improved scheme's
+    departure is much smaller.  Below the cylinder (gas) for the 31 / 34 deg
+    cases (rho_w = 4.5, phi = 1.4), above it (inside the droplet) for the
+    121 / 125 deg cases (rho_w = 1.5, drho = 0.5).  A layer node departs from
+    the bulk by more than 50 % (gas side) or 5 % (liquid side)."""
+    bottom, top = CC[1] - RC - 1, CC[1] + RC + 1  # first fluid nodes on x = N_x / 2
+    rg, rl = _run(oracle_mod, gpu_lib, "vd_4.5", 8)[4:6]
+    lay = {}
+    for key in ("vd_4.5", "ivd_phi1.4"):
+        prof = _run(oracle_mod, gpu_lib, key, 8)[6]
+        lay[key] = _layer(prof, bottom, -1, rg, 0.5)
+    for key in ("vd_1.5", "ivd_drho0.5"):
+        prof = _run(oracle_mod, gpu_lib, key, 8)[6]
+        lay[key] = _layer(prof, top, +1, rl, 0.05)
+    print("layer thickness (nodes):", lay)
+    assert 3 <= lay["vd_4.5"] <= 6 and lay["ivd_phi1.4"] <= 1
+    assert 3 <= lay["vd_1.5"] <= 6 and lay["ivd_drho0.5"] <= 1
