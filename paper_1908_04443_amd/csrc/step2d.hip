@@ -36,7 +36,7 @@ namespace lbm {
 // The work of one TX x TY tile at (x0, y0) of an nx x ny lattice; shared by
 // the single-lattice kernel and the multi-case kernel.  part: index of this
 // tile's diagnostic partial; list_tile: its entry block in the wall lists.
-template <typename real, int TX, int TY, int NT, int MODE, bool BUF>
+template <typename real, int TX, int TY, int NT, int MODE, bool BUF, bool GFW>
 __device__ __forceinline__ void d2q9_tile(const Coef<real>& C, const Fields<real>& Fd,
                                           const FieldOut<real>& Out, const int nx, const int ny,
                                           const int x0, const int y0, const int part,
@@ -51,7 +51,7 @@ __device__ __forceinline__ void d2q9_tile(const Coef<real>& C, const Fields<real
     const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
     bool bad = false;
     real f[RPT][9];
-    d2q9_prologue<real, TX, TY, NT, BUF>(C, Fd, io, nx, ny, x0, y0, list_tile, S, f, bad);
+    d2q9_prologue<real, TX, TY, NT, BUF, GFW>(C, Fd, io, nx, ny, x0, y0, list_tile, S, f, bad);
 
     double d_sum = 0.0;
     real d_umax = real(0), d_rmin = real(1e30), d_rmax = real(-1e30);
@@ -136,7 +136,8 @@ __device__ __forceinline__ void d2q9_tile(const Coef<real>& C, const Fields<real
 // gets a contiguous range of the order, so neighbouring tiles share an L2).
 // ORD > 0: the order runs through column groups ORD tiles wide, row by row
 // inside a group, so the tile above a tile is only ORD places earlier.
-template <typename real, int TX, int TY, int NT, int MODE, bool XCD, bool BUF, int ORD, int OCC>
+template <typename real, int TX, int TY, int NT, int MODE, bool XCD, bool BUF, int ORD, int OCC,
+          bool GFW>
 __global__ __launch_bounds__(NT, OCC) void k_step_d2q9(Coef<real> C, Fields<real> Fd,
                                                        FieldOut<real> Out) {
     const int gxb = gridDim.x, gyb = gridDim.y, nblk = gxb * gyb;
@@ -152,8 +153,8 @@ __global__ __launch_bounds__(NT, OCC) void k_step_d2q9(Coef<real> C, Fields<real
         bx = bid % gxb;
         by = bid / gxb;
     }
-    d2q9_tile<real, TX, TY, NT, MODE, BUF>(C, Fd, Out, C.nx, C.ny, bx * TX, by * TY, bid,
-                                           by * gxb + bx);
+    d2q9_tile<real, TX, TY, NT, MODE, BUF, GFW>(C, Fd, Out, C.nx, C.ny, bx * TX, by * TY, bid,
+                                                by * gxb + bx);
 }
 
 // Many independent lattices in one launch: workgroup -> (case, tile) through
@@ -178,7 +179,8 @@ __global__ __launch_bounds__(NT) void k_step_d2q9_batch(Coef<real> C, BatchArgs<
     Fd.tw_stride = B.tw_stride;
     Fd.tw_code = B.tw_code;
     FieldOut<real> none{nullptr, nullptr, nullptr};
-    d2q9_tile<real, TX, TY, NT, MODE_STEP, BUF>(C, Fd, none, cd.nx, cd.ny, t.x0, t.y0, bid, bid);
+    d2q9_tile<real, TX, TY, NT, MODE_STEP, BUF, false>(C, Fd, none, cd.nx, cd.ny, t.x0, t.y0, bid,
+                                                    bid);
 }
 
 // ----------------------------------------------------------------- launch
@@ -225,20 +227,21 @@ int grid2d_blocks(int nx, int ny, int variant) {
     return ((nx + s.TX - 1) / s.TX) * ((ny + s.TY - 1) / s.TY);
 }
 
-template <typename real, int V, int MODE, bool BUF = true>
+template <typename real, int V, int MODE, bool BUF = true, bool GFW = false>
 static void launch_v(const Coef<real>& C, const Fields<real>& F, const FieldOut<real>& O,
                      hipStream_t s) {
     constexpr Shape2D sh = Variants2D<real>::shape[V];
     dim3 grid((C.nx + sh.TX - 1) / sh.TX, (C.ny + sh.TY - 1) / sh.TY);
-    hipLaunchKernelGGL((k_step_d2q9<real, sh.TX, sh.TY, sh.NT, MODE, sh.xcd, BUF, sh.ord, sh.occ>),
-                       grid, dim3(sh.NT), 0, s, C, F, O);
+    hipLaunchKernelGGL(
+        (k_step_d2q9<real, sh.TX, sh.TY, sh.NT, MODE, sh.xcd, BUF, sh.ord, sh.occ, GFW>), grid,
+        dim3(sh.NT), 0, s, C, F, O);
 }
 
-template <typename real, int MODE, bool BUF, size_t... I>
+template <typename real, int MODE, bool BUF, bool GFW, size_t... I>
 static auto table_v(std::index_sequence<I...>) {
     using Fn = void (*)(const Coef<real>&, const Fields<real>&, const FieldOut<real>&,
                         hipStream_t);
-    return std::array<Fn, sizeof...(I)>{&launch_v<real, (int)I, MODE, BUF>...};
+    return std::array<Fn, sizeof...(I)>{&launch_v<real, (int)I, MODE, BUF, GFW>...};
 }
 
 // population arrays of 4 GiB or more cannot use 32-bit buffer offsets
@@ -250,20 +253,25 @@ static bool fits_buffer(const Coef<real>& C, int Q) {
 template <typename real>
 hipError_t launch_step2d(const Coef<real>& C, const Fields<real>& F, const FieldOut<real>& O,
                          int mode, int variant, hipStream_t s) {
+    const bool gf = C.scheme == WET_GF;
     if (mode == MODE_FIELDS) variant = 0;
     if (!fits_buffer(C, 9)) {
-        if (mode == MODE_STEP) launch_v<real, 0, MODE_STEP, false>(C, F, O, s);
+        if (mode == MODE_STEP && gf) launch_v<real, 0, MODE_STEP, false, true>(C, F, O, s);
+        else if (mode == MODE_STEP) launch_v<real, 0, MODE_STEP, false>(C, F, O, s);
+        else if (gf) launch_v<real, 0, MODE_FIELDS, false, true>(C, F, O, s);
         else launch_v<real, 0, MODE_FIELDS, false>(C, F, O, s);
         return hipGetLastError();
     }
     // the sweep kernels have no geometric formulation: its steps run tiled
-    if (variant >= Variants2D<real>::count && C.scheme == WET_GF) variant = Variants2D<real>::preferred;
+    if (variant >= Variants2D<real>::count && gf) variant = Variants2D<real>::preferred;
     if (variant >= Variants2D<real>::count)
         return launch_step2d_march<real>(C, F, O, variant - Variants2D<real>::count, s);
     if (variant < 0) return hipErrorInvalidValue;
     constexpr auto seq = std::make_index_sequence<Variants2D<real>::count>{};
-    static const auto step = table_v<real, MODE_STEP, true>(seq);
-    if (mode == MODE_STEP) step[variant](C, F, O, s);
+    static const auto step = table_v<real, MODE_STEP, true, false>(seq);
+    static const auto step_gf = table_v<real, MODE_STEP, true, true>(seq);
+    if (mode == MODE_STEP) (gf ? step_gf : step)[variant](C, F, O, s);
+    else if (gf) launch_v<real, 0, MODE_FIELDS, true, true>(C, F, O, s);
     else launch_v<real, 0, MODE_FIELDS, true>(C, F, O, s);
     return hipGetLastError();
 }

@@ -93,7 +93,9 @@ __device__ __forceinline__ real gf_density(const uint8_t* cls, const real* rho, 
     return r[0] >= r[1] ? r[0] : r[1];
 }
 
-template <typename real, int TX, int TY, int NT, bool BUF>
+// GFW: the geometric formulation is compiled in (a separate instantiation,
+// so that the other schemes keep its registers out of their kernels)
+template <typename real, int TX, int TY, int NT, bool BUF, bool GFW = false>
 __device__ __forceinline__ void d2q9_prologue(const Coef<real>& C, const Fields<real>& Fd,
                                               const PopIO<real, BUF>& io, const int nx,
                                               const int ny, const int x0, const int y0,
@@ -126,7 +128,8 @@ __device__ __forceinline__ void d2q9_prologue(const Coef<real>& C, const Fields<
     // Per-tile wall list (improved virtual density): the first wave loads
     // the first 64 entries with the other loads of this phase; entries
     // beyond 64 (rare) follow after the barrier.
-    const bool wl_on = (C.scheme == WET_IVD || C.scheme == WET_GF) && Fd.tw_pack != nullptr;
+    const bool gf = GFW && C.scheme == WET_GF;
+    const bool wl_on = (C.scheme == WET_IVD || gf) && Fd.tw_pack != nullptr;
     uint32_t wl_e0 = 0;
     int wl_pos = -1;
     int32_t wl_code = 0;
@@ -137,7 +140,7 @@ __device__ __forceinline__ void d2q9_prologue(const Coef<real>& C, const Fields<
             const int w = Fd.tw_pack[wl_e0 + tid];
             wl_phi = Fd.tw_phi[wl_e0 + tid];
             wl_drho = Fd.tw_drho[wl_e0 + tid];
-            if (C.scheme == WET_GF) wl_code = Fd.tw_code[wl_e0 + tid];
+            if (gf) wl_code = Fd.tw_code[wl_e0 + tid];
             if (tid < (w >> 16)) wl_pos = w & 0xFFFF;
             if (tid == 0) S.wl_count = w >> 16;
         }
@@ -201,7 +204,7 @@ __device__ __forceinline__ void d2q9_prologue(const Coef<real>& C, const Fields<
         wl_pos = Fd.tw_pack[wl_e0 + tid] & 0xFFFF;
         wl_phi = Fd.tw_phi[wl_e0 + tid];
         wl_drho = Fd.tw_drho[wl_e0 + tid];
-        if (C.scheme == WET_GF) wl_code = Fd.tw_code[wl_e0 + tid];
+        if (gf) wl_code = Fd.tw_code[wl_e0 + tid];
     }
 
     // psi on tile + 1 halo; wall nodes first get their virtual density
@@ -237,7 +240,7 @@ __device__ __forceinline__ void d2q9_prologue(const Coef<real>& C, const Fields<
                 rw = rw < C.rho_g ? C.rho_g : rw;
                 S.rho[p] = rw;
                 ps = psi_of(C, rw, bad);
-            } else if (C.scheme == WET_GF) {
+            } else if (gf) {
                 const int kw = Fd.widx[S.row[ly] + S.col[lx]];
                 const real rw = gf_density<real, LX>(S.cls, S.rho, p, Fd.gfcode[kw], Fd.phi[kw],
                                                      Fd.drho[kw]);
@@ -252,7 +255,7 @@ __device__ __forceinline__ void d2q9_prologue(const Coef<real>& C, const Fields<
         }
         S.psi[p] = ps;
     }
-    if (wl_pos >= 0 && C.scheme == WET_GF) {
+    if (wl_pos >= 0 && gf) {
         const real rw = gf_density<real, LX>(S.cls, S.rho, wl_pos, wl_code, wl_phi, wl_drho);
         S.rho[wl_pos] = rw;
         S.psi[wl_pos] = psi_of(C, rw, bad);
