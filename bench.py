@@ -229,9 +229,21 @@ def cpu_baseline(data, lbm_params, steps):
     O.run(op, solid, f0, steps, phi, drho)
     dt = time.perf_counter() - t0
     N = 2048 * 2048
-    return dict(value=N * steps / dt / 1e6, unit="MLUPS", cores=O.get_threads(), kind="oracle",
+    threads = O.get_threads()
+    # the same oracle on one thread, a shorter sample
+    s1 = max(1, steps // 20)
+    O.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        O.run(op, solid, f0, s1, phi, drho)
+        dt1 = time.perf_counter() - t0
+    finally:
+        O.set_threads(threads)
+    return dict(value=N * steps / dt / 1e6, unit="MLUPS", cores=threads, kind="oracle",
                 sample=f"D2Q9 2048x2048 porous workload, same initial state, {steps} FP64 "
-                       f"oracle steps ({dt:.1f} s)")
+                       f"oracle steps ({dt:.1f} s)",
+                value_1thread=N * s1 / dt1 / 1e6,
+                sample_1thread=f"{s1} steps on one thread ({dt1:.1f} s)")
 
 
 def copy_calibration(nbytes, reps):
@@ -318,6 +330,8 @@ def main():
                      "kernel_ms": round(kern_s * 1e3, 5)},
         "check": {"mass_rel_drift": c1["mass_drift"], "max_u": c1["max_u"],
                   "rho_min_max": c1["rho"]},
+        "env": {"device": torch.cuda.get_device_name(0), "hip": torch.version.hip,
+                "torch": torch.__version__},
     }
 
     want = set() if args.no_secondary else set(x for x in args.secondary.split(",") if x)
