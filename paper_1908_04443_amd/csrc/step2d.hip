@@ -256,10 +256,15 @@ hipError_t launch_step2d(const Coef<real>& C, const Fields<real>& F, const Field
     const bool gf = C.scheme == WET_GF;
     if (mode == MODE_FIELDS) variant = 0;
     if (!fits_buffer(C, 9)) {
-        if (mode == MODE_STEP && gf) launch_v<real, 0, MODE_STEP, false, true>(C, F, O, s);
-        else if (mode == MODE_STEP) launch_v<real, 0, MODE_STEP, false>(C, F, O, s);
-        else if (gf) launch_v<real, 0, MODE_FIELDS, false, true>(C, F, O, s);
-        else launch_v<real, 0, MODE_FIELDS, false>(C, F, O, s);
+        // one tile shape serves arrays past 4 GiB; the wall lists were built
+        // for the context's shape, so the walls are looked up per node here
+        Fields<real> G = F;
+        G.tw_pack = nullptr;
+        G.tw_code = nullptr;
+        if (mode == MODE_STEP && gf) launch_v<real, 0, MODE_STEP, false, true>(C, G, O, s);
+        else if (mode == MODE_STEP) launch_v<real, 0, MODE_STEP, false>(C, G, O, s);
+        else if (gf) launch_v<real, 0, MODE_FIELDS, false, true>(C, G, O, s);
+        else launch_v<real, 0, MODE_FIELDS, false>(C, G, O, s);
         return hipGetLastError();
     }
     // the sweep kernels have no geometric formulation: its steps run tiled

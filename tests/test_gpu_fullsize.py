@@ -2,15 +2,8 @@
 configuration that bench.py times.
 
 The oracle cannot step a 2048^2 or 256^3 lattice in seconds, so these tests
-compare sampled outputs it can compute on their own.  One step of the method
-at node x reads populations no farther than 3 nodes away (Chebyshev
-distance): streaming from x - e (1), the force there needs psi of its
-neighbours (2), and a wall neighbour's virtual density needs the density of
-its own fluid neighbours (3).  After K steps, a node's state therefore
-depends only on the initial state within 3K nodes.  The oracle steps a
-periodic crop of the initial state around each sample; nodes farther than
-3K from the crop's edge are unaffected by the crop's artificial wrap and
-must equal the full-lattice GPU result.
+compare sampled outputs it can compute on their own: oracle windows (see
+windows.py), periodic crops of the initial state around sampled points.
 
 Every input comes from the seeded workload builders, with the oracle's
 thermodynamic constants; the GPU run uses the library's default tile variant
@@ -21,86 +14,9 @@ import pytest
 
 from cases import SIGMA_CAL, SIGMA_CS075, lib_params, oracle_params
 from paper_1908_04443_amd import workloads as W
+from windows import TOL_RHO, TOL_U, compare_windows, gpu_run
 
 pytestmark = pytest.mark.gpu
-
-TOL_RHO = 1e-4   # FP32 vs FP64 oracle, normwise relative on rho
-TOL_U = 1e-3     # normwise relative on u
-
-
-def _gpu_run(L, op, solid, rho0, phi_f, drho_f, nsteps, precision=4, graph_steps=None):
-    import torch
-    p = lib_params(L, op, dict(precision=precision))
-    s = L.Solver(p, max(int(solid.sum()), 1))
-    s.set_geometry(solid)
-    walls = s.wall_nodes()
-    phi = torch.as_tensor(phi_f.ravel()[walls], dtype=s.dtype, device=s.device)
-    drho = torch.as_tensor(drho_f.ravel()[walls], dtype=s.dtype, device=s.device)
-    s.set_wetting(L.LBM_WET_IVD, 0.0, phi if len(walls) else None, drho if len(walls) else None)
-    s.set_fields(rho0.ravel())
-    if graph_steps:
-        s.set_graph_steps(graph_steps)
-    variant = s.variant
-    rc0, d0 = s.diagnostics()
-    s.step(nsteps)
-    rc1, d1 = s.diagnostics()
-    out = s.get_fields(rho=True, u=True)
-    torch.cuda.synchronize()
-    rho = out["rho"].double().cpu().numpy().reshape(solid.shape)
-    u = out["u"].double().cpu().numpy().reshape((-1,) + solid.shape)
-    s.close()
-    assert rc0 == 0 and rc1 == 0
-    return rho, u, variant, d0, d1
-
-
-def _crop(a, origin, size):
-    """Periodic crop of the last len(origin) axes: origin in (z,) y, x order."""
-    idx = [np.arange(o, o + size) % n for o, n in zip(origin, a.shape[-len(origin):])]
-    return a[(Ellipsis,) + np.ix_(*idx)]
-
-
-def _oracle_window(O, case, solid, rho0, phi_f, drho_f, origin, size, nsteps):
-    kw = dict(case, nx=size, ny=size)
-    if case.get("lattice", 9) == 19:
-        kw["nz"] = size
-    op = oracle_params(O, kw)
-    s_w = np.ascontiguousarray(_crop(solid, origin, size))
-    r_w = np.ascontiguousarray(_crop(rho0, origin, size))
-    walls = O.wall_nodes(op, s_w)
-    phi = _crop(phi_f, origin, size).ravel()[walls]
-    drho = _crop(drho_f, origin, size).ravel()[walls]
-    f = O.run(op, s_w, O.init_eq(op, s_w, r_w), nsteps, phi, drho)
-    rho, u, _ = O.fields(op, s_w, f, phi, drho)
-    shape = s_w.shape
-    return rho.reshape(shape), u.reshape((-1,) + shape)
-
-
-def _compare_windows(O, case, solid, rho0, phi_f, drho_f, rho_g, u_g, origins, size, nsteps):
-    """rho: normwise relative per window.  u: max abs difference over all
-    windows relative to the largest oracle speed in them (a window in a
-    region at rest has no velocity scale of its own)."""
-    m = 3 * nsteps + 1  # margin untouched by the crop's wrap
-    core = slice(m, size - m)
-    assert size - 2 * m >= 8
-    worst_r = du = u_scale = 0.0
-    for org in origins:
-        rho_o, u_o = _oracle_window(O, case, solid, rho0, phi_f, drho_f, org, size, nsteps)
-        sl = (core,) * len(org)
-        ro = rho_o[sl]
-        rg = _crop(rho_g, org, size)[sl]
-        uo = u_o[(slice(None),) + sl]
-        ug = _crop(u_g, org, size)[(slice(None),) + sl]
-        er = np.abs(rg - ro).max() / np.abs(ro).max()
-        eu = np.abs(ug - uo).max()
-        print(f"window {org}: rho {er:.2e}  |du| {eu:.2e}  (|u|max {np.abs(uo).max():.2e})",
-              flush=True)
-        worst_r, du = max(worst_r, er), max(du, eu)
-        u_scale = max(u_scale, np.abs(uo).max())
-    print(f"worst rho {worst_r:.2e}, worst u {du / u_scale:.2e} of {u_scale:.2e}", flush=True)
-    assert u_scale > 1e-3  # the windows include moving fluid
-    assert worst_r <= TOL_RHO
-    assert du / u_scale <= TOL_U
-
 
 def test_c1_2048_porous_sampled_windows(oracle_mod, gpu_lib):
     """2048^2 porous medium, FP32, default tile variant, 50 steps: 8 windows
@@ -112,7 +28,7 @@ def test_c1_2048_porous_sampled_windows(oracle_mod, gpu_lib):
     op = oracle_params(O, case)
     d = W.c1_porous(op.rho_g, op.rho_l)
     K, size = 50, 340
-    rho_g, u_g, variant, d0, d1 = _gpu_run(L, op, d["solid"], d["rho"], d["phi"], d["drho"], K)
+    rho_g, u_g, variant, d0, d1 = gpu_run(L, op, d["solid"], d["rho"], d["phi"], d["drho"], K)
     drift = abs(d1["mass"] - d0["mass"]) / d0["mass"]
     print(f"variant {variant}, mass drift {drift:.2e}", flush=True)
     assert drift < 1e-6
@@ -121,7 +37,7 @@ def test_c1_2048_porous_sampled_windows(oracle_mod, gpu_lib):
     for (cx, cy, r) in d["cyl"][:2]:  # a cylinder surface at the window centre
         origins.append((int(cy) - size // 2, int(cx + r) - size // 2))
     origins += [tuple(int(v) for v in rng.integers(0, 2048, 2)) for _ in range(5)]
-    _compare_windows(O, case, d["solid"], d["rho"], d["phi"], d["drho"], rho_g, u_g,
+    compare_windows(O, case, d["solid"], d["rho"], d["phi"], d["drho"], rho_g, u_g,
                      origins, size, K)
 
 
@@ -136,7 +52,7 @@ def test_c2_256cubed_sphere_sampled_windows(oracle_mod, gpu_lib):
     op = oracle_params(O, case)
     d = W.c2_sphere(op.rho_g, op.rho_l)
     K, size = 8, 64
-    rho_g, u_g, variant, d0, d1 = _gpu_run(L, op, d["solid"], d["rho"], d["phi"], d["drho"], K)
+    rho_g, u_g, variant, d0, d1 = gpu_run(L, op, d["solid"], d["rho"], d["phi"], d["drho"], K)
     drift = abs(d1["mass"] - d0["mass"]) / d0["mass"]
     print(f"variant {variant}, mass drift {drift:.2e}", flush=True)
     assert drift < 1e-6
@@ -150,7 +66,7 @@ def test_c2_256cubed_sphere_sampled_windows(oracle_mod, gpu_lib):
                (228, 128, 128),   # top of the droplet interface
                (35, 232, 250)]    # wraps in y and x
     origins = [(z - h, y - h, x - h) for z, y, x in centres]
-    _compare_windows(O, case, d["solid"], d["rho"], d["phi"], d["drho"], rho_g, u_g,
+    compare_windows(O, case, d["solid"], d["rho"], d["phi"], d["drho"], rho_g, u_g,
                      origins, size, K)
 
 
