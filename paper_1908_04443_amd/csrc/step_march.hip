@@ -28,6 +28,9 @@
 #ifndef LBM_PREC
 #define LBM_PREC 0
 #endif
+#include <array>
+#include <utility>
+
 #include "lbm_device.hpp"
 #include "lbm_kernels.hpp"
 
@@ -56,9 +59,16 @@ static void launch_density(const Coef<real>& C, const Fields<real>& F, hipStream
                        F.rho, N);
 }
 
-template <typename L, typename real, int TX, int TY, int TZ, int MODE, bool XCD, bool BUF>
-__global__ __launch_bounds__(TX* TY) void k_step_march(Coef<real> C, Fields<real> Fd,
-                                                       FieldOut<real> Out) {
+// FUSED: no density pass.  Phase A loads the populations of its slice,
+// sums the density of every node of the slice (owned and halo) itself and
+// keeps the owned node's populations in registers until phase C collides
+// them two iterations later (a ring of three register sets, so the loop
+// body is instantiated three times with the sets rotated).
+// OCC: minimum waves per SIMD asked of the register allocator.
+template <typename L, typename real, int TX, int TY, int TZ, int MODE, bool XCD, bool BUF,
+          bool FUSED = false, int OCC = 1>
+__global__ __launch_bounds__(TX* TY, OCC) void k_step_march(Coef<real> C, Fields<real> Fd,
+                                                            FieldOut<real> Out) {
     constexpr bool D3 = (L::D == 3);
     constexpr int Q = L::Q;
     constexpr int NT = TX * TY;
@@ -125,18 +135,44 @@ __global__ __launch_bounds__(TX* TY) void k_step_march(Coef<real> C, Fields<real
     real d_umax = real(0), d_rmin = real(1e30), d_rmax = real(-1e30);
     int d_cnt = 0;
 
-    for (int it = 0; it < TZ + 4; ++it) {
+    // Rl: populations of the owned node of slice c0 - 2 + it (fused only);
+    // Rc: those of slice c0 - 4 + it, loaded two iterations earlier
+    auto body = [&](const int it, real (&Rl)[Q], real (&Rc)[Q]) __attribute__((always_inline)) {
         // ---------------- A: slice c0 - 2 + it
         {
             const int slot = it % NSLOT;
             const int cz = wrapi(c0 - 2 + it, nc);
             const uint32_t base = (uint32_t)cz * nab;
-            // densities come from the density pass: one value per node
-            s_cls[slot][own_p] = Fd.cls[base + own_ab];
-            s_rho[slot][own_p] = Fd.rho[base + own_ab];
-            if (tid < RING) {
-                s_cls[slot][ring_p] = Fd.cls[base + ring_ab];
-                s_rho[slot][ring_p] = Fd.rho[base + ring_ab];
+            if constexpr (FUSED) {
+                // density of each node in velocity order, 0 off the fluid
+                const uint8_t oc = Fd.cls[base + own_ab];
+#pragma unroll
+                for (int a = 0; a < Q; ++a) Rl[a] = io.ld(a, base + own_ab);
+                uint8_t rc = CLS_SOLID;
+                real rr = real(0);
+                if (tid < RING) {
+                    rc = Fd.cls[base + ring_ab];
+                    rr = io.ld(0, base + ring_ab);
+#pragma unroll
+                    for (int a = 1; a < Q; ++a) rr += io.ld(a, base + ring_ab);
+                }
+                real r = Rl[0];
+#pragma unroll
+                for (int a = 1; a < Q; ++a) r += Rl[a];
+                s_cls[slot][own_p] = oc;
+                s_rho[slot][own_p] = oc == CLS_FLUID ? r : real(0);
+                if (tid < RING) {
+                    s_cls[slot][ring_p] = rc;
+                    s_rho[slot][ring_p] = rc == CLS_FLUID ? rr : real(0);
+                }
+            } else {
+                // densities come from the density pass: one value per node
+                s_cls[slot][own_p] = Fd.cls[base + own_ab];
+                s_rho[slot][own_p] = Fd.rho[base + own_ab];
+                if (tid < RING) {
+                    s_cls[slot][ring_p] = Fd.cls[base + ring_ab];
+                    s_rho[slot][ring_p] = Fd.rho[base + ring_ab];
+                }
             }
         }
         __syncthreads();
@@ -247,7 +283,7 @@ __global__ __launch_bounds__(TX* TY) void k_step_march(Coef<real> C, Fields<real
                 }
                 real fl[Q];
 #pragma unroll
-                for (int a = 0; a < Q; ++a) fl[a] = io.ld(a, n);
+                for (int a = 0; a < Q; ++a) fl[a] = FUSED ? Rc[a] : io.ld(a, n);
                 if (MODE == MODE_FIELDS) {
                     real j[3] = {real(0), real(0), real(0)};
 #pragma unroll
@@ -299,6 +335,17 @@ __global__ __launch_bounds__(TX* TY) void k_step_march(Coef<real> C, Fields<real
         }
         // no barrier here: the next phase A writes slot (it+1) mod 5, which
         // phase C of this iteration does not read (it reads it-3 .. it-1)
+    };
+    if constexpr (FUSED) {
+        real R0[Q], R1[Q], R2[Q];
+        for (int it = 0; it < TZ + 4; it += 3) {
+            body(it, R0, R1);
+            if (it + 1 < TZ + 4) body(it + 1, R1, R2);
+            if (it + 2 < TZ + 4) body(it + 2, R2, R0);
+        }
+    } else {
+        real R0[Q];
+        for (int it = 0; it < TZ + 4; ++it) body(it, R0, R0);
     }
 
     if (MODE == MODE_FIELDS && Out.part) {
@@ -313,22 +360,27 @@ __global__ __launch_bounds__(TX* TY) void k_step_march(Coef<real> C, Fields<real
 struct Shape3D {
     int TX, TY, TZ;
     bool xcd;
+    bool fused;  // densities summed in the sweep (no density pass)
+    int occ;     // minimum waves per SIMD asked of the register allocator
 };
 
 template <typename real>
 struct Variants3D;
 template <>
 struct Variants3D<float> {
-    static constexpr int count = 5;
+    static constexpr int count = 7;
     static constexpr int preferred = 2;  // 32 x 8 cross-section, chunks of 8 slices
     static constexpr Shape3D shape[count] = {
-        {32, 8, 16, true}, {32, 8, 16, false}, {32, 8, 8, true}, {32, 8, 32, true}, {16, 16, 16, true}};
+        {32, 8, 16, true, false, 1}, {32, 8, 16, false, false, 1}, {32, 8, 8, true, false, 1},
+        {32, 8, 32, true, false, 1}, {16, 16, 16, true, false, 1}, {32, 8, 16, true, true, 1},
+        {32, 8, 32, true, true, 1}};
 };
 template <>
 struct Variants3D<double> {
-    static constexpr int count = 2;
+    static constexpr int count = 3;
     static constexpr int preferred = 0;
-    static constexpr Shape3D shape[count] = {{32, 8, 16, true}, {32, 8, 16, false}};
+    static constexpr Shape3D shape[count] = {
+        {32, 8, 16, true, false, 1}, {32, 8, 16, false, false, 1}, {32, 8, 16, true, true, 1}};
 };
 
 template <typename real>
@@ -353,38 +405,38 @@ static void launch_v3(const Coef<real>& C, const Fields<real>& F, const FieldOut
                       hipStream_t s) {
     constexpr Shape3D sh = Variants3D<real>::shape[V];
     dim3 grid((C.nx + sh.TX - 1) / sh.TX, (C.ny + sh.TY - 1) / sh.TY, (C.nz + sh.TZ - 1) / sh.TZ);
-    hipLaunchKernelGGL((k_step_march<D3Q19, real, sh.TX, sh.TY, sh.TZ, MODE, sh.xcd, BUF>), grid,
-                       dim3(sh.TX * sh.TY), 0, s, C, F, O);
+    hipLaunchKernelGGL(
+        (k_step_march<D3Q19, real, sh.TX, sh.TY, sh.TZ, MODE, sh.xcd, BUF, sh.fused, sh.occ>), grid,
+        dim3(sh.TX * sh.TY), 0, s, C, F, O);
 }
 
-template <typename real, int V>
-static void launch_mode3(const Coef<real>& C, const Fields<real>& F, const FieldOut<real>& O,
-                         int mode, hipStream_t s) {
-    if (mode == MODE_STEP) launch_v3<real, V, MODE_STEP>(C, F, O, s);
-    else launch_v3<real, V, MODE_FIELDS>(C, F, O, s);
+template <typename real, size_t... I>
+static auto table_v3(std::index_sequence<I...>) {
+    using Fn = void (*)(const Coef<real>&, const Fields<real>&, const FieldOut<real>&,
+                        hipStream_t);
+    return std::array<Fn, sizeof...(I)>{&launch_v3<real, (int)I, MODE_STEP>...};
 }
 
 template <typename real>
 hipError_t launch_step3d(const Coef<real>& C, const Fields<real>& F, const FieldOut<real>& O,
                          int mode, int variant, hipStream_t s) {
     if (mode == MODE_FIELDS) variant = 0;
-    launch_density<19, real>(C, F, s);
+    if (variant < 0 || variant >= Variants3D<real>::count) return hipErrorInvalidValue;
     // population arrays of 4 GiB or more cannot use 32-bit buffer offsets
     if ((uint64_t)19 * (uint64_t)C.nx * C.ny * C.nz * sizeof(real) > 0xFFFFFFFFull) {
+        launch_density<19, real>(C, F, s);
         if (mode == MODE_STEP) launch_v3<real, 0, MODE_STEP, false>(C, F, O, s);
         else launch_v3<real, 0, MODE_FIELDS, false>(C, F, O, s);
         return hipGetLastError();
     }
-    if (variant == 0) launch_mode3<real, 0>(C, F, O, mode, s);
-    else if (variant == 1) launch_mode3<real, 1>(C, F, O, mode, s);
-    else if constexpr (Variants3D<real>::count > 2) {
-        if (variant == 2) launch_mode3<real, 2>(C, F, O, mode, s);
-        else if (variant == 3) launch_mode3<real, 3>(C, F, O, mode, s);
-        else if (variant == 4) launch_mode3<real, 4>(C, F, O, mode, s);
-        else return hipErrorInvalidValue;
-    } else {
-        return hipErrorInvalidValue;
+    if (mode == MODE_FIELDS) {
+        launch_density<19, real>(C, F, s);
+        launch_v3<real, 0, MODE_FIELDS>(C, F, O, s);
+        return hipGetLastError();
     }
+    if (!Variants3D<real>::shape[variant].fused) launch_density<19, real>(C, F, s);
+    static const auto tab = table_v3<real>(std::make_index_sequence<Variants3D<real>::count>{});
+    tab[variant](C, F, O, s);
     return hipGetLastError();
 }
 
