@@ -184,7 +184,8 @@ def run_c4(L, W, T=1000, K=50):
     d = W.c4_adjoint(p.rho_g, p.rho_l)
     s, nw = setup_solver(L, W, p, d, int(d["solid"].sum()))
     s.step(50)
-    fwd_ms = s.step_timed(T) / T
+    # medians of 5 runs: the 256^2 step is short enough for launch jitter to show
+    fwd_ms = float(np.median([s.step_timed(T) / T for _ in range(5)]))
     s.set_fields(d["rho"].ravel())
     ckpt = s.ckpt_buffer(T, K)
     torch.cuda.synchronize()
@@ -196,11 +197,14 @@ def run_c4(L, W, T=1000, K=50):
     fluid = torch.as_tensor(d["solid"].ravel() == 0, device="cuda")
     seed = torch.where(fluid, 2.0 * (rho_T - 0.5 * (p.rho_g + p.rho_l)), torch.zeros_like(rho_T))
     s.adjoint(seed, T, K, ckpt)  # warm
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    gp, gd = s.adjoint(seed, T, K, ckpt)
-    torch.cuda.synchronize()
-    adj_ms = (time.perf_counter() - t0) * 1e3
+    runs = []
+    for _ in range(5):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gp, gd = s.adjoint(seed, T, K, ckpt)
+        torch.cuda.synchronize()
+        runs.append((time.perf_counter() - t0) * 1e3)
+    adj_ms = float(np.median(runs))
     nseg = (T + K - 1) // K
     recompute = T - nseg
     adj_step_ms = (adj_ms - recompute * fwd_ms) / T
