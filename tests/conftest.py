@@ -22,7 +22,7 @@ def oracle_mod():
 
 @pytest.fixture(scope="session")
 def gpu_lib():
-    """The built HIP library on a GPU machine; builds it only if nothing is built."""
+    """The built HIP library on a machine with a GPU; builds it only if nothing is built."""
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")

@@ -178,10 +178,10 @@ def test_droplet_impact_schemes(oracle_mod, gpu_lib):
     at (150, 180), droplet r = 50 at (150, 310) falling at U0 = 0.06,
     Re = U0 2r / nu = 600 (nu = 0.01), theta about 60 deg through
     rho_w = 3.45 (VD), theta_a = 63.5 deg (GF) and phi = 1.135 (IVD).
-    The paper: the constant virtual density surrounds the cylinder with a
-    mass-transfer layer (its droplet touches the cylinder early) and its
-    results drift away from the geometric formulation, while the improved
-    scheme stays consistent with it.  Checked: at t = 100 the density of the
+    In the paper's comparison, the constant virtual density wraps the
+    cylinder in a mass-transfer layer (so its droplet meets the cylinder
+    early) and its fields depart from the geometric formulation's, while the
+    improved scheme follows the geometric formulation.  Checked: at t = 100 the density of the
     fluid node next to the top of the cylinder is at least twice as high
     with VD as with GF or IVD, and at t = 300, 4000 and 10000 the IVD field stays within a fifth
     of VD's mean distance from the GF field."""

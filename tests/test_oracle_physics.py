@@ -155,10 +155,10 @@ def _poiseuille_error(O, scheme, phi=1.0, drho=0.0, rho_w=0.0, steps=30000):
 def test_poiseuille_between_plates(oracle_mod):
     """Sec. IV B, Fig. 12: with the improved virtual density the velocity
     profile matches the analytic Poiseuille profile whatever the wall
-    parameter (the paper: excellent agreement); with the constant virtual
-    density close to the gas density a thick mass-transfer layer forms at
-    the plates and the profile deviates (the paper: E_r of 7.7 % and 22.9 %
-    at about 113 and 158 deg).  Here rho_w = 1.5 (about 120 deg on the
+    parameter (the paper reports no visible deviation); with the constant
+    virtual density close to the gas density a thick mass-transfer layer
+    forms at the plates and the profile deviates (relative errors of 7.7 %
+    and 22.9 % reported at about 113 and 158 deg).  Here rho_w = 1.5 (about 120 deg on the
     cylinder of Fig. 4c)."""
     O = oracle_mod
     e_ivd = _poiseuille_error(O, "ivd", phi=1.0)
