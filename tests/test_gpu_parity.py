@@ -72,6 +72,26 @@ def test_c0_fp32_mass_conservation(oracle_mod, gpu_lib):
     assert drift <= 1e-7
 
 
+def test_c0_equilibrium_angle_fp32_vs_oracle(oracle_mod, gpu_lib):
+    """The 128^2 case run to equilibrium (20000 steps): the contact angle of
+    the FP32 GPU run within 0.5 deg of the FP64 oracle's (both measured by
+    the same circle fit of the droplet's free interface)."""
+    from paper_1908_04443_amd import analysis as A
+    O = oracle_mod
+    s = Setup(O, dict(C0, precision=4))
+    steps = 20000
+    res = run_gpu(gpu_lib, s, steps)
+    f = O.run(s.op, s.solid, s.f0, steps, s.phi, s.drho)
+    rho_o, _, _ = O.fields(s.op, s.solid, f, s.phi, s.drho)
+    angles = []
+    for rho in (res["rho"], rho_o):
+        th, fit = A.contact_angle_cylinder(rho.reshape(128, 128), s.solid, (64, 64), 24,
+                                           s.op.rho_g, s.op.rho_l, select=lambda x, y: y > 64)
+        angles.append(th)
+    print(f"theta FP32 GPU {angles[0]:.3f}, FP64 oracle {angles[1]:.3f}", flush=True)
+    assert abs(angles[0] - angles[1]) <= 0.5
+
+
 @pytest.mark.parametrize("scheme", ["ivd", "vd", "sfi"])
 def test_ragged_schemes_fp64(oracle_mod, gpu_lib, scheme):
     # sizes that leave partial tiles in both directions
