@@ -186,7 +186,10 @@ int lbm_set_wetting(lbm_ctx* ctx, int32_t scheme, double scalar,
 
 /* Initial state f = f_eq(rho, u) on fluid nodes (0 on solid).  rho_dev: N
  * reals; u_dev: D*N reals ([D][N]) or NULL for rest.  Errors: LBM_ESTATE
- * (no geometry). */
+ * (no geometry).  Densities are not checked against the range where Eq. 6
+ * is real: the next step raises the device domain flag, which the next
+ * lbm_get_diagnostics reports as LBM_EDOMAIN.  Clears that flag and the
+ * sticky error. */
 int lbm_set_fields(lbm_ctx* ctx, const void* rho_dev, const void* u_dev);
 /* Raw state: f_dev holds Q*N reals ([Q][N]), copied in (checkpoint
  * restore).  Values on solid nodes are ignored. */
@@ -215,8 +218,11 @@ int lbm_get_diagnostics(lbm_ctx* ctx, lbm_diag* host_out);
 int lbm_step_timed(lbm_ctx* ctx, int64_t nsteps, double* ms_total);
 
 /* ------------------------------------------------------------ tuning */
-/* The step kernel exists in several tile shapes (and workgroup orderings).
- * Number of variants for a lattice/precision; LBM_EINVAL if unknown. */
+/* The step kernel exists in several tile shapes (and workgroup orderings;
+ * for D3Q19 also with or without a separate density pass).  Number of
+ * variants for a lattice/precision; LBM_EINVAL if unknown.  A lattice whose
+ * population array exceeds 4 GiB runs one shape with 64-bit addressing
+ * whatever the variant. */
 int lbm_variant_count(int32_t lattice, int32_t precision);
 int lbm_set_variant(lbm_ctx* ctx, int32_t variant);
 int lbm_get_variant(lbm_ctx* ctx, int32_t* variant);

@@ -200,8 +200,9 @@ def blob_rho(shape, seed, rho_g, rho_l, solid=None, sigma=16.0, sigma2=1.5):
 def angle_to_params(theta_deg, table):
     """Map prescribed angles to (phi, drho) by monotone linear interpolation
     in a calibration table {"theta": [...], "phi": [...], "drho": [...]}
-    sorted by theta.  Angles below 90 deg use phi >= 1 with drho = 0, angles
-    above 90 deg use phi = 1 with drho >= 0."""
+    sorted by theta.  A table whose rows hold either phi >= 1 with drho = 0
+    (below the standard-case angle) or phi = 1 with drho >= 0 (above it),
+    with the standard case itself as a row, keeps that split."""
     th = np.asarray(table["theta"], dtype=np.float64)
     ph = np.asarray(table["phi"], dtype=np.float64)
     dr = np.asarray(table["drho"], dtype=np.float64)

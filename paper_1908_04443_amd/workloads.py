@@ -20,12 +20,15 @@ import numpy as np
 from . import inputs as I
 
 # Prescribed angle -> (phi, drho) of the improved virtual-density scheme for
-# the Carnahan-Starling fluid at 0.75 Tc (tau = 1, sigma = 0.1071).  Angles
-# below 90 deg use phi >= 1, above 90 deg use drho >= 0 (Sec. III B).
+# the Carnahan-Starling fluid at 0.75 Tc (tau = 1, sigma = 0.1071): static
+# angles of droplets on a flat wall measured with the CPU oracle
+# (tests/golden/calibrate_angles.py, angle_calibration_cs075.json).  Angles
+# below the standard case (phi = 1, drho = 0: 84.66 deg) use phi > 1, above
+# it drho > 0 (Sec. III B); 20 and 160 deg extend the end segments.
 ANGLE_TABLE_CS075 = {
-    "theta": [20.0, 30.0, 45.0, 60.0, 75.0, 90.0, 105.0, 120.0, 135.0, 150.0, 160.0],
-    "phi": [1.60, 1.45, 1.30, 1.20, 1.10, 1.00, 1.00, 1.00, 1.00, 1.00, 1.00],
-    "drho": [0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.008, 0.016, 0.026, 0.040, 0.052],
+    "theta": [20.0, 30.0, 45.0, 60.0, 75.0, 84.66, 90.0, 105.0, 120.0, 135.0, 150.0, 160.0],
+    "phi": [1.9097, 1.7636, 1.5401, 1.3001, 1.1013, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0],
+    "drho": [0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.00421, 0.01596, 0.02799, 0.03774, 0.04608, 0.05139],
 }
 
 # sigma of Eq. 7 per (EOS, T/Tc, lattice), from the flat-slab calibration in

@@ -262,3 +262,38 @@ def test_mass_transfer_layer_profiles(oracle_mod, gpu_lib):
     print("layer thickness (nodes):", lay)
     assert 3 <= lay["vd_4.5"] <= 6 and lay["ivd_phi1.4"] <= 1
     assert 3 <= lay["vd_1.5"] <= 6 and lay["ivd_drho0.5"] <= 1
+
+
+@pytest.mark.parametrize("theta", [45.0, 75.0, 105.0, 135.0])
+def test_angle_table_reproduced_by_the_gpu(oracle_mod, gpu_lib, theta):
+    """The calibrated angle table of the benchmark inputs (CS at 0.75 Tc,
+    measured with the oracle on a flat wall) reproduced by the FP32 GPU
+    path: the same flat-wall droplet at the table's (phi, drho) for a
+    target angle between calibration points settles within 2 deg of it."""
+    import torch
+    from paper_1908_04443_amd import workloads as W
+    O, L = oracle_mod, gpu_lib
+    nx, ny, r0 = 320, 80, 20.0
+    phi, drho = I.angle_to_params(theta, W.ANGLE_TABLE_CS075)
+    case = dict(nx=nx, ny=ny, T_ratio=0.75, sigma=SIGMA_CAL["cs_0.75"]["sigma"], tau=1.0,
+                scheme="ivd", precision=4)
+    op = oracle_params(O, case)
+    solid = np.zeros((ny, nx), np.uint8)
+    solid[0:4, :] = 1
+    rho0 = I.droplet_rho((ny, nx), (nx / 2.0, 4.0 + 0.6 * r0), r0, op.rho_g, op.rho_l,
+                         solid=solid)
+    s = L.Solver(lib_params(L, op, case), int(solid.sum()))
+    s.set_geometry(solid)
+    nw = len(s.wall_nodes())
+    s.set_wetting(L.LBM_WET_IVD, 0.0,
+                  torch.full((nw,), float(phi), dtype=s.dtype, device=s.device),
+                  torch.full((nw,), float(drho), dtype=s.dtype, device=s.device))
+    s.set_fields(rho0.ravel())
+    s.step(15000)
+    rho = s.get_fields(rho=True, u=False)["rho"].double().cpu().numpy().reshape(ny, nx)
+    s.close()
+    th, _ = A.contact_angle_flat(rho, solid, 3.5, op.rho_g, op.rho_l,
+                                 select=lambda x, y: y < ny - 4)
+    print(f"target {theta}: phi {float(phi):.4f} drho {float(drho):.5f} -> {th:.2f} deg",
+          flush=True)
+    assert abs(th - theta) <= 2.0
