@@ -234,8 +234,10 @@ int lbm_get_variant(lbm_ctx* ctx, int32_t* variant);
  * the state advances by nvariants*(steps+2) steps.  ms_per_variant (host,
  * nullable, lbm_variant_count entries) receives the mean step time of each.
  * If the environment variable LBM_AUTOTUNE_CACHE names a file, a cached
- * choice for the same lattice, precision and size is used without timing
- * (unless ms_per_variant is requested), and new results are appended. */
+ * choice for the same lattice, precision and size (for a multi-case
+ * context: the same number and sizes of cases) is used without timing
+ * (unless ms_per_variant is requested; the last matching line wins), and
+ * new results are appended as one line each. */
 int lbm_autotune(lbm_ctx* ctx, int64_t steps, void* save_dev, int32_t* best_out,
                  double* ms_per_variant);
 

@@ -1061,16 +1061,27 @@ int lbm_autotune(lbm_ctx* c, int64_t steps, void* save_dev, int32_t* best_out,
     const int nv = ctx_variants(c);
     const size_t fbytes = state_bytes(c);
     const char* cache = std::getenv("LBM_AUTOTUNE_CACHE");
-    char key[160];
-    std::snprintf(key, sizeof key, "lattice=%d precision=%d nx=%d ny=%d nz=%d cases=%d",
+    // the problem a cached choice applies to: lattice, precision, size, and
+    // for a multi-case context the count and sizes of its cases (FNV-1a)
+    uint64_t sizes = 1469598103934665603ull;
+    for (const lbm_case& k : c->cases) {
+        for (const uint64_t v : {(uint64_t)k.nx, (uint64_t)k.ny}) {
+            sizes ^= v;
+            sizes *= 1099511628211ull;
+        }
+    }
+    char key[192];
+    std::snprintf(key, sizeof key, "lattice=%d precision=%d nx=%d ny=%d nz=%d cases=%d sizes=%016llx",
                   c->p.lattice, c->p.precision, c->p.nx, c->p.ny, c->p.nz,
-                  c->is_batch ? (int)c->cases.size() : 1);
+                  c->is_batch ? (int)c->cases.size() : 1, (unsigned long long)sizes);
+    const size_t klen = std::strlen(key);
     if (cache && !ms_per_variant) {
         if (FILE* fp = std::fopen(cache, "r")) {
             char line[256];
             int found = -1;
             while (std::fgets(line, sizeof line, fp)) {
-                if (std::strncmp(line, key, std::strlen(key)) == 0) {
+                // the whole key, then the separator before "variant="
+                if (std::strncmp(line, key, klen) == 0 && line[klen] == ' ') {
                     const char* v = std::strstr(line, "variant=");
                     if (v) found = std::atoi(v + 8);
                 }

@@ -142,3 +142,45 @@ def test_degenerate_d3q19_lattices(oracle_mod, gpu_lib, shape):
     s.f0 = oracle_mod.init_eq(s.op, s.solid, rho)
     res = run_gpu(gpu_lib, s, 20)
     _compare(oracle_mod, s, res, 20, 1e-12, 1e-12)
+
+
+def test_autotune_cache_file(gpu_lib, tmp_path, monkeypatch):
+    """LBM_AUTOTUNE_CACHE: a tuned choice is appended as one line; a later
+    call on the same problem takes the last matching line without timing;
+    a line whose key only starts like this problem's does not match."""
+    import torch
+    L = gpu_lib
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("LBM_AUTOTUNE_CACHE", str(path))
+    p = _params(L, precision=4, nx=40, ny=24)
+    s = L.Solver(p, 64)
+    solid = np.zeros((24, 40), np.uint8)
+    solid[8:14, 10:18] = 1
+    s.set_geometry(solid)
+    s.set_wetting(L.LBM_WET_IVD, 0.0, None, None)
+    s.set_fields(np.where(solid.ravel() != 0, 0.0, 0.2))
+    best = s.autotune(steps=2)
+    lines = path.read_text().splitlines()
+    assert len(lines) == 1 and f"variant={best} " in lines[0]
+    key = lines[0].split(" variant=")[0]
+    nv = L.lbm_variant_count(9, 4)
+    other = (best + 1) % nv
+    with open(path, "a") as fh:
+        fh.write(f"{key} variant={other} ms=0\n")
+        fh.write(f"{key}0 variant={(best + 2) % nv} ms=0\n")  # longer key: no match
+    assert s.autotune(steps=2) == other
+    assert s.variant == other
+    assert len(path.read_text().splitlines()) == 3  # nothing timed, nothing appended
+    s.step(2)
+    torch.cuda.synchronize()
+    s.close()
+    # another size has another key: timed and appended
+    q = L.Solver(_params(L, precision=4, nx=41, ny=24), 64)
+    solid2 = np.zeros((24, 41), np.uint8)
+    solid2[8:14, 10:18] = 1
+    q.set_geometry(solid2)
+    q.set_wetting(L.LBM_WET_IVD, 0.0, None, None)
+    q.set_fields(np.where(solid2.ravel() != 0, 0.0, 0.2))
+    q.autotune(steps=2)
+    assert len(path.read_text().splitlines()) == 4
+    q.close()
