@@ -49,7 +49,7 @@ extern "C" {
 enum {
     LBM_OK = 0,
     LBM_EINVAL = -1,  /* invalid argument or parameter */
-    LBM_ENOMEM = -2,  /* workspace too small */
+    LBM_ENOMEM = -2,  /* workspace too small, or host allocation failed */
     LBM_EDOMAIN = -3, /* psi argument negative or NaN (Eq. 6 undefined) */
     LBM_ESTATE = -4,  /* call out of order (e.g. step before geometry) */
     LBM_EDEVICE = -5  /* HIP runtime error */

@@ -785,7 +785,7 @@ int lbm_create(const lbm_params* p, void* stream, void* workspace, size_t ws_byt
         return fail(LBM_ENOMEM, "workspace needs " + std::to_string(need) + " bytes");
     if (((uintptr_t)workspace & 255) != 0) return fail(LBM_EINVAL, "workspace must be 256-byte aligned");
     lbm_ctx* c = new (std::nothrow) lbm_ctx();
-    if (!c) return fail(LBM_EINVAL, "host allocation failed");
+    if (!c) return fail(LBM_ENOMEM, "host allocation failed");
     c->p = *p;
     c->Q = p->lattice;
     c->D = p->lattice == 9 ? 2 : 3;
@@ -803,7 +803,7 @@ int lbm_create(const lbm_params* p, void* stream, void* workspace, size_t ws_byt
         c->variant = p->precision == 4 ? step3d_preferred_variant<float>()
                                        : step3d_preferred_variant<double>();
     if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
-        delete c;
+        lbm_destroy(c);  // releases whichever event was created
         return fail(LBM_EDEVICE, "hipEventCreate failed");
     }
     *out = c;
@@ -1158,7 +1158,7 @@ int lbm_create_batch(const lbm_params* p, int32_t ncases, const int32_t* nx, con
         return fail(LBM_ENOMEM, "workspace needs " + std::to_string(need) + " bytes");
     if (((uintptr_t)workspace & 255) != 0) return fail(LBM_EINVAL, "workspace must be 256-byte aligned");
     lbm_ctx* c = new (std::nothrow) lbm_ctx();
-    if (!c) return fail(LBM_EINVAL, "host allocation failed");
+    if (!c) return fail(LBM_ENOMEM, "host allocation failed");
     c->p = *p;
     c->p.nx = c->p.ny = c->p.nz = 0;
     c->Q = 9;
@@ -1170,7 +1170,7 @@ int lbm_create_batch(const lbm_params* p, int32_t ncases, const int32_t* nx, con
     c->is_batch = true;
     layout_batch(*p, ncases, nx, ny, n_wall_max, c);
     if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
-        delete c;
+        lbm_destroy(c);  // releases whichever event was created
         return fail(LBM_EDEVICE, "hipEventCreate failed");
     }
     rc = c->prec == 4 ? upload_cases<float>(c) : upload_cases<double>(c);
