@@ -286,10 +286,11 @@ static int capture_graph(lbm_ctx* c, const Coef<real>& C) {
 }
 
 // Per-tile wall lists of the D2Q9 tile step under the improved
-// virtual-density scheme: for every tile, the wall nodes of the tile plus
-// its 1-node ring (the ones whose virtual density the tile forms, Eqs.
-// 16-17) with their LDS positions, so that the step kernel fetches their phi
-// and drho with its first loads instead of through a dependent wall-index
+// virtual-density scheme and the geometric formulation: for every tile, the
+// wall nodes of the tile plus its 1-node ring (the ones whose virtual
+// density the tile forms, Eqs. 16-17 or Eq. 11) with their LDS positions,
+// so that the step kernel fetches their phi and drho (or stencil code and
+// weights) with its first loads instead of through a dependent wall-index
 // lookup.  Entry block t belongs to the t-th tile in the kernel's numbering
 // (row-major for one lattice, table order for a multi-case context).  Lists
 // are off (stride 0) when a tile would hold more than 256 entries or the

@@ -3,8 +3,9 @@
 // (x0, y0) it loads node classes of the tile plus a 2-node halo, the
 // populations of the owned nodes into registers, the density of the tile
 // plus 2-node halo, the wall virtual densities (Eqs. 16-17 with the
-// limiter, the constant virtual density, or none for Eq. 8) and psi
-// (Eq. 6) on the tile plus a 1-node halo, all in LDS.
+// limiter, the constant virtual density, the geometric formulation of
+// Eq. 11, or none for Eq. 8) and psi (Eq. 6) on the tile plus a 1-node
+// halo, all in LDS.
 #pragma once
 #include "lbm_device.hpp"
 #include "lbm_kernels.hpp"
@@ -125,9 +126,9 @@ __device__ __forceinline__ void d2q9_prologue(const Coef<real>& C, const Fields<
         else S.row[i - LX] = (uint32_t)wrapi(y0 - 2 + (i - LX), ny) * (uint32_t)nx;
     }
 
-    // Per-tile wall list (improved virtual density): the first wave loads
-    // the first 64 entries with the other loads of this phase; entries
-    // beyond 64 (rare) follow after the barrier.
+    // Per-tile wall list (improved virtual density, geometric formulation):
+    // the first wave loads the first 64 entries with the other loads of
+    // this phase; entries beyond 64 (rare) follow after the barrier.
     const bool gf = GFW && C.scheme == WET_GF;
     const bool wl_on = (C.scheme == WET_IVD || gf) && Fd.tw_pack != nullptr;
     uint32_t wl_e0 = 0;
