@@ -344,8 +344,10 @@ def main():
         # one read of every fluid population per diagnostics call
         "diagnostics": {"ms_per_call": round(c1["diag_ms"], 4),
                         "achieved_read_GBs": round(9 * 4 * nf / c1["diag_ms"] / 1e6, 1)},
-        "env": {"device": torch.cuda.get_device_name(0), "hip": torch.version.hip,
-                "torch": torch.__version__},
+        "env": {"device": torch.cuda.get_device_name(0),
+                "arch": getattr(torch.cuda.get_device_properties(0), "gcnArchName", ""),
+                "cus": torch.cuda.get_device_properties(0).multi_processor_count,
+                "hip": torch.version.hip, "torch": torch.__version__},
     }
 
     want = set() if args.no_secondary else set(x for x in args.secondary.split(",") if x)
