@@ -24,6 +24,11 @@ SOURCES = ["api.cpp", "thermo.cpp", "geometry.cpp", "step2d.hip", "step_march.hi
 SPLIT = {"step2d.hip", "step_march.hip", "adjoint2d.hip"}
 EXTRA_SOURCES = []
 
+# a plain C program that uses the library through include/lbm.h only
+DEMO_SRC = os.path.join(CSRC, "cabi_demo.c")
+DEMO = os.path.join(HERE, "lbm_cabi_demo")
+INCLUDE = os.path.join(os.path.dirname(HERE), "include")
+
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
@@ -87,6 +92,13 @@ def build(verbose=False, jobs=8):
     _run(["g++", "-shared", "-o", tmp, *objs, f"-L{tlib}", "-lamdhip64",
           f"-Wl,-rpath,{tlib}", "-Wl,--no-undefined", "-Wl,--disable-new-dtags"], verbose)
     os.replace(tmp, LIB)
+    # the C demo: gcc, C11, HIP runtime C API; finds liblbm.so next to itself
+    dtmp = DEMO + ".tmp"
+    _run(["gcc", "-std=c11", "-O2", "-Wall", "-Wextra", "-D__HIP_PLATFORM_AMD__",
+          "-I/opt/rocm/include", f"-I{INCLUDE}", DEMO_SRC, "-o", dtmp, f"-L{HERE}", "-llbm",
+          f"-L{tlib}", "-lamdhip64", "-lm", "-Wl,-rpath,$ORIGIN", f"-Wl,-rpath,{tlib}",
+          "-Wl,--disable-new-dtags"], verbose)
+    os.replace(dtmp, DEMO)
     return LIB
 
 

@@ -139,3 +139,15 @@ def test_eos_domain(L):
     p.eos_T = 2.0  # supercritical: no coexistence
     g, l = C.c_double(), C.c_double()
     assert L.lib().lbm_eos_coexistence(C.byref(p), C.byref(g), C.byref(l)) == L.LBM_EINVAL
+
+
+def test_c_program_links_against_the_library(L):
+    """The plain C consumer of include/lbm.h (csrc/cabi_demo.c) is built with
+    the library and resolves liblbm.so and the HIP runtime at load time."""
+    import subprocess
+    from paper_1908_04443_amd import build
+    if not os.path.exists(build.DEMO):
+        build.build()
+    out = subprocess.run(["ldd", build.DEMO], capture_output=True, text=True, check=True).stdout
+    assert "liblbm.so" in out and "libamdhip64" in out
+    assert "not found" not in out
