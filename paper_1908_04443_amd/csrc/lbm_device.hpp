@@ -202,6 +202,24 @@ struct PopIO {
         if constexpr (BUF) buf_st<real>(v, rout, n * (uint32_t)sizeof(real), (uint32_t)a * N * (uint32_t)sizeof(real));
         else fout[(size_t)a * N + n] = v;
     }
+    // push with halfway bounce-back in one store: to slot a of node
+    // n + delta if `stream`, else to slot b of node n (delta uniform across
+    // the wavefront).  The smaller of the two slot offsets goes into the
+    // scalar offset and the per-lane offset selects the rest, so a
+    // wavefront with both kinds of lanes issues one store, not two.
+    // Needs n + delta >= 0.
+    __device__ __forceinline__ void st_push(bool stream, int a, int b, int delta, uint32_t n,
+                                            real v) const {
+        const int lo = a < b ? a : b;
+        if constexpr (BUF) {
+            const uint32_t ds = (uint32_t)((int)((a - lo) * N) + delta);
+            const uint32_t db = (uint32_t)(b - lo) * N;
+            buf_st<real>(v, rout, (n + (stream ? ds : db)) * (uint32_t)sizeof(real),
+                         (uint32_t)lo * N * (uint32_t)sizeof(real));
+        } else {
+            fout[stream ? (int64_t)a * N + n + delta : (int64_t)b * N + n] = v;
+        }
+    }
     // store to node n + delta of direction a, delta uniform across the
     // wavefront: the shift goes into the scalar offset, so every direction
     // shares the per-lane offset of n.  Needs a * N + delta >= 0.

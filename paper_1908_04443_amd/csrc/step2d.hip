@@ -109,8 +109,8 @@ __device__ __forceinline__ void d2q9_tile(const Coef<real>& C, const Fields<real
 #pragma unroll
             for (int a = 0; a < 9; ++a) {
                 const int q = p + L::ex[a] + L::ey[a] * LX;
-                if (S.cls[q] == CLS_FLUID) io.st_shift(a, L::ex[a] + L::ey[a] * nx, n, fs[a]);
-                else io.st(L::opp[a], n, fs[a]);
+                io.st_push(S.cls[q] == CLS_FLUID, a, L::opp[a], L::ex[a] + L::ey[a] * nx, n,
+                           fs[a]);
             }
         } else {
 #pragma unroll
