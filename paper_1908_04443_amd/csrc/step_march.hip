@@ -354,6 +354,172 @@ __global__ __launch_bounds__(TX* TY, OCC) void k_step_march(Coef<real> C, Fields
     if (bad) Fd.flag[0] = 1;
 }
 
+
+// D3Q19 step on a TX x TY x TZ brick with no march: after the density pass,
+// one load phase brings the node classes and densities of the brick plus a
+// 2-node halo in every direction (one value per node, mostly from L2) and
+// each thread's TZ owned nodes' populations into registers; psi (with the
+// wall virtual densities) follows on the brick plus a 1-node halo, then the
+// owned nodes collide and push.  Two barriers per brick and no dependent
+// chain along z, so many independent workgroups hide the memory latency.
+// Step mode only (the field/diagnostic pass uses the sweep).
+template <typename real, int TX, int TY, int TZ, bool XCD>
+__global__ __launch_bounds__(TX* TY) void k_step_brick(Coef<real> C, Fields<real> Fd) {
+    using L = D3Q19;
+    constexpr int Q = 19, NT = TX * TY;
+    constexpr int PX = TX + 4, PY = TY + 4, PZ = TZ + 4, PXY = PX * PY, PS = PXY * PZ;
+    __shared__ uint8_t s_cls[PS];
+    __shared__ real s_rho[PS];
+    __shared__ real s_psi[PS];
+
+    const int na = C.nx, nb = C.ny, nc = C.nz;
+    const uint32_t nab = (uint32_t)na * (uint32_t)nb;
+    const uint32_t N = nab * (uint32_t)nc;
+    const PopIO<real, true> io(Fd.fin, Fd.fout, N, Q);
+    const int tid = threadIdx.x;
+    const int nblk = gridDim.x * gridDim.y * gridDim.z;
+    int bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    if (XCD) bid = remap_xcd(bid, nblk);
+    const int bx = bid % gridDim.x, by = (bid / gridDim.x) % gridDim.y;
+    const int bz = bid / (gridDim.x * gridDim.y);
+    const int a0 = bx * TX, b0 = by * TY, c0 = bz * TZ;
+    const int tx = tid % TX, ty = tid / TX;
+    bool bad = false;
+
+    // ---- one load phase: classes and densities of the halo box, owned populations
+    const int ga = a0 + tx, gb = b0 + ty;
+    const bool own_xy = ga < na && gb < nb;
+    const uint32_t own_ab = (uint32_t)wrapi(gb, nb) * na + wrapi(ga, na);
+    real f[TZ][Q];
+#pragma unroll
+    for (int k = 0; k < TZ; ++k) {
+        const uint32_t n = (uint32_t)wrapi(c0 + k, nc) * nab + own_ab;
+#pragma unroll
+        for (int a = 0; a < Q; ++a) f[k][a] = io.ld(a, n);
+    }
+    constexpr int JB = (PS + NT - 1) / NT;
+    uint8_t hc[JB];
+    real hr[JB];
+#pragma unroll
+    for (int j = 0; j < JB; ++j) {
+        const int i = tid + j * NT;
+        hc[j] = CLS_SOLID;
+        hr[j] = real(0);
+        if (i < PS) {
+            const int lx = i % PX, ly = (i / PX) % PY, lz = i / PXY;
+            const uint32_t n = (uint32_t)wrapi(c0 - 2 + lz, nc) * nab +
+                               (uint32_t)wrapi(b0 - 2 + ly, nb) * na + wrapi(a0 - 2 + lx, na);
+            hc[j] = Fd.cls[n];
+            hr[j] = Fd.rho[n];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < JB; ++j) {
+        const int i = tid + j * NT;
+        if (i < PS) {
+            s_cls[i] = hc[j];
+            s_rho[i] = hr[j];
+        }
+    }
+    __syncthreads();
+
+    // ---- psi on the brick plus a 1-node halo; wall nodes get their virtual density
+    constexpr int IX = TX + 2, IY = TY + 2, IZ = TZ + 2;
+    for (int i = tid; i < IX * IY * IZ; i += NT) {
+        const int lx = 1 + i % IX, ly = 1 + (i / IX) % IY, lz = 1 + i / (IX * IY);
+        const int p = (lz * PY + ly) * PX + lx;
+        const uint8_t c = s_cls[p];
+        real ps = real(0);
+        if (c == CLS_FLUID) {
+            ps = psi_of(C, s_rho[p], bad);
+        } else if (c == CLS_WALL) {
+            if (C.scheme == WET_IVD) {
+                // Eq. 17 over the fluid neighbours, Eq. 16 and the limiter
+                real num = real(0), den = real(0);
+                bool first = true;
+#pragma unroll
+                for (int a = 1; a < Q; ++a) {
+                    const int q = p + L::ex[a] + L::ey[a] * PX + L::ez[a] * PXY;
+                    if (s_cls[q] == CLS_FLUID) {
+                        const real w = real(L::w12[a]) * real(1.0 / 12.0);
+                        num = first ? w * s_rho[q] : num + w * s_rho[q];
+                        den = first ? w : den + w;
+                        first = false;
+                    }
+                }
+                const real rave = num / den;
+                const uint32_t n = (uint32_t)wrapi(c0 - 2 + lz, nc) * nab +
+                                   (uint32_t)wrapi(b0 - 2 + ly, nb) * na + wrapi(a0 - 2 + lx, na);
+                const int kw = Fd.widx[n];
+                real rw = Fd.phi[kw] * rave - Fd.drho[kw];
+                rw = rw > C.rho_l ? C.rho_l : rw;
+                rw = rw < C.rho_g ? C.rho_g : rw;
+                ps = psi_of(C, rw, bad);
+            } else if (C.scheme == WET_VD) {
+                ps = C.psi_w;
+            }
+        }
+        s_psi[p] = ps;
+    }
+    __syncthreads();
+
+    // ---- owned nodes: force (Eq. 5, Eq. 8), collision, push with bounce-back
+#pragma unroll
+    for (int k = 0; k < TZ; ++k) {
+        const int gc = c0 + k;
+        if (!own_xy || gc >= nc) continue;  // ragged brick: not owned
+        const int p = ((k + 2) * PY + ty + 2) * PX + tx + 2;
+        if (s_cls[p] != CLS_FLUID) continue;
+        const uint32_t n = (uint32_t)gc * nab + own_ab;
+        const real rho = s_rho[p];
+        const real psi_c = s_psi[p];
+        real sm[3] = {real(0), real(0), real(0)}, sa[3] = {real(0), real(0), real(0)};
+#pragma unroll
+        for (int a = 1; a < Q; ++a) {
+            const int q = p + L::ex[a] + L::ey[a] * PX + L::ez[a] * PXY;
+            const real w = real(L::w12[a]) * real(1.0 / 12.0);
+            // FP32: w (psi(x+e) - psi(x)), equal since sum w e = 0
+            const real wp = (sizeof(real) == 4) ? w * (s_psi[q] - psi_c) : w * s_psi[q];
+            const int e3[3] = {L::ex[a], L::ey[a], L::ez[a]};
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                if (e3[d] == 1) sm[d] += wp;
+                if (e3[d] == -1) sm[d] -= wp;
+            }
+            if (C.scheme == WET_SFI && s_cls[q] != CLS_FLUID) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    if (e3[d] == 1) sa[d] += w;
+                    if (e3[d] == -1) sa[d] -= w;
+                }
+            }
+        }
+        real Fm[3], F[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            Fm[d] = -C.G * psi_c * sm[d];
+            const real fa = (C.scheme == WET_SFI) ? -C.G_w * rho * sa[d] : real(0);
+            F[d] = Fm[d] + fa + C.body[d];
+        }
+        real fs[Q], u[3];
+        collide<L, real>(C, f[k], rho, F, Fm, psi_c, fs, u);
+#pragma unroll
+        for (int a = 0; a < Q; ++a) {
+            const int q = p + L::ex[a] + L::ey[a] * PX + L::ez[a] * PXY;
+            if (s_cls[q] == CLS_FLUID) {
+                int ta = ga + L::ex[a], tb = gb + L::ey[a], tc = gc + L::ez[a];
+                ta = ta < 0 ? ta + na : (ta >= na ? ta - na : ta);
+                tb = tb < 0 ? tb + nb : (tb >= nb ? tb - nb : tb);
+                tc = tc < 0 ? tc + nc : (tc >= nc ? tc - nc : tc);
+                io.st(a, (uint32_t)tc * nab + (uint32_t)tb * na + ta, fs[a]);
+            } else {
+                io.st(L::opp[a], n, fs[a]);
+            }
+        }
+    }
+    if (bad) Fd.flag[0] = 1;
+}
+
 // ----------------------------------------------------------------- launch
 // Sweep-tile variants the autotuner chooses among (variant 0: default and
 // the shape of the field/diagnostic mode).
@@ -362,25 +528,28 @@ struct Shape3D {
     bool xcd;
     bool fused;  // densities summed in the sweep (no density pass)
     int occ;     // minimum waves per SIMD asked of the register allocator
+    bool brick;  // k_step_brick: no march, TZ slices per thread
 };
 
 template <typename real>
 struct Variants3D;
 template <>
 struct Variants3D<float> {
-    static constexpr int count = 7;
+    static constexpr int count = 8;
     static constexpr int preferred = 2;  // 32 x 8 cross-section, chunks of 8 slices
     static constexpr Shape3D shape[count] = {
-        {32, 8, 16, true, false, 1}, {32, 8, 16, false, false, 1}, {32, 8, 8, true, false, 1},
-        {32, 8, 32, true, false, 1}, {16, 16, 16, true, false, 1}, {32, 8, 16, true, true, 1},
-        {32, 8, 32, true, true, 1}};
+        {32, 8, 16, true, false, 1, false}, {32, 8, 16, false, false, 1, false},
+        {32, 8, 8, true, false, 1, false},  {32, 8, 32, true, false, 1, false},
+        {16, 16, 16, true, false, 1, false}, {32, 8, 16, true, true, 1, false},
+        {32, 8, 32, true, true, 1, false},  {32, 8, 2, true, false, 1, true}};
 };
 template <>
 struct Variants3D<double> {
-    static constexpr int count = 3;
+    static constexpr int count = 4;
     static constexpr int preferred = 0;
     static constexpr Shape3D shape[count] = {
-        {32, 8, 16, true, false, 1}, {32, 8, 16, false, false, 1}, {32, 8, 16, true, true, 1}};
+        {32, 8, 16, true, false, 1, false}, {32, 8, 16, false, false, 1, false},
+        {32, 8, 16, true, true, 1, false}, {32, 8, 2, true, false, 1, true}};
 };
 
 template <typename real>
@@ -405,9 +574,13 @@ static void launch_v3(const Coef<real>& C, const Fields<real>& F, const FieldOut
                       hipStream_t s) {
     constexpr Shape3D sh = Variants3D<real>::shape[V];
     dim3 grid((C.nx + sh.TX - 1) / sh.TX, (C.ny + sh.TY - 1) / sh.TY, (C.nz + sh.TZ - 1) / sh.TZ);
-    hipLaunchKernelGGL(
-        (k_step_march<D3Q19, real, sh.TX, sh.TY, sh.TZ, MODE, sh.xcd, BUF, sh.fused, sh.occ>), grid,
-        dim3(sh.TX * sh.TY), 0, s, C, F, O);
+    if constexpr (sh.brick && MODE == MODE_STEP && BUF)
+        hipLaunchKernelGGL((k_step_brick<real, sh.TX, sh.TY, sh.TZ, sh.xcd>), grid,
+                           dim3(sh.TX * sh.TY), 0, s, C, F);
+    else
+        hipLaunchKernelGGL(
+            (k_step_march<D3Q19, real, sh.TX, sh.TY, sh.TZ, MODE, sh.xcd, BUF, sh.fused, sh.occ>),
+            grid, dim3(sh.TX * sh.TY), 0, s, C, F, O);
 }
 
 template <typename real, size_t... I>
