@@ -390,14 +390,16 @@ def test_complex_step_matches_central_differences(oracle_mod):
 
 
 # ------------------------------------------------------- forces at a flat wall
+@pytest.mark.parametrize("lattice", [9, 19])
 @pytest.mark.parametrize("scheme,par", [("ivd", 1.0), ("ivd", 1.1), ("vd", 0.25), ("sfi", 0.3)])
-def test_flat_wall_forces_closed_form(oracle_mod, scheme, par):
+def test_flat_wall_forces_closed_form(oracle_mod, scheme, par, lattice):
     """Uniform fluid of density rho0 between flat walls (two solid rows,
     periodic lattice).  The fluid row touching a wall sees, in Eq. 5, the
     wall's psi on its three wall-side links (weights 1/3 + 2/12 = 1/2 in
     total), and under the solid-fluid interaction the adhesion of Eq. 8 on
     the same links; every other fluid row sees a uniform neighbourhood.  So
-    the total force is, normal to the wall and into the fluid,
+    the total force is, normal to the wall and into the fluid (the wall-side
+    weights also sum to 1/2 in D3Q19: one link of 1/6 and four of 1/12),
       psi0 (psi0 - psi_w) / 2                       (virtual-density schemes)
       psi0^2 / 2 + G_w rho0 / 2                     (solid-fluid interaction,
                                                      psi = 0 on solid nodes)
@@ -405,33 +407,38 @@ def test_flat_wall_forces_closed_form(oracle_mod, scheme, par):
     (the neighbour mean is rho0), the constant rho_w for the other; zero
     elsewhere and zero along the wall."""
     O = oracle_mod
-    nx, ny, rho0 = 6, 10, 0.2
-    kw = dict(nx=nx, ny=ny, sigma=0.105)
+    nx, ny, rho0 = 6, 10, 0.2  # ny: the axis normal to the walls (z in 3-D)
+    if lattice == 9:
+        kw, shape, D = dict(nx=nx, ny=ny, sigma=0.105), (ny, nx), 2
+    else:
+        kw, shape, D = dict(lattice=19, nx=nx, ny=4, nz=ny, sigma=0.105), (ny, 4, nx), 3
     if scheme == "ivd":
         op = O.make_params(scheme=O.IVD, **kw)
     elif scheme == "vd":
         op = O.make_params(scheme=O.VD, rho_w=par, **kw)
     else:
         op = O.make_params(scheme=O.SFI, G_w=par, **kw)
-    solid = np.zeros((ny, nx), np.uint8)
-    solid[0:2, :] = 1
+    solid = np.zeros(shape, np.uint8)
+    solid[0:2] = 1
     rho_init = np.where(solid != 0, 0.0, rho0)
     nw = len(O.wall_nodes(op, solid))
-    assert nw == 2 * nx  # both solid rows touch fluid (row 1 below, row 0 through the wrap)
+    assert nw == 2 * solid[0].size  # both solid layers touch fluid (one through the wrap)
     phi = np.full(nw, par if scheme == "ivd" else 1.0)
     f0 = O.init_eq(op, solid, rho_init)
     rho, _, F = O.fields(op, solid, f0, phi, np.zeros(nw))
-    F = F.reshape(2, ny, nx)
+    F = F.reshape((D,) + shape)
+    Fn, Ft = F[D - 1], F[:D - 1]  # normal and tangential components
+    rho = rho.reshape(shape)
     psi0 = np.sqrt(O.psi_arg(op, rho0))
     if scheme == "sfi":
         mag = 0.5 * psi0 ** 2 + 0.5 * par * rho0
     else:
         rw = min(max(par * rho0, op.rho_g), op.rho_l) if scheme == "ivd" else par
         mag = 0.5 * psi0 * (psi0 - np.sqrt(O.psi_arg(op, rw)))
-        assert np.allclose(rho.reshape(ny, nx)[0:2], rw, rtol=0, atol=1e-15)
-    assert np.abs(F[0]).max() < 1e-15                          # nothing along the wall
-    assert np.allclose(F[1, 2], mag, rtol=1e-13, atol=1e-17)   # above the lower wall face
-    assert np.allclose(F[1, ny - 1], -mag, rtol=1e-13, atol=1e-17)  # below the upper face
-    assert np.abs(F[1, 3:ny - 1]).max() < 1e-15                # uniform neighbourhoods
+        assert np.allclose(rho[0:2], rw, rtol=0, atol=1e-15)
+    assert np.abs(Ft).max() < 1e-15                          # nothing along the wall
+    assert np.allclose(Fn[2], mag, rtol=1e-13, atol=1e-17)   # above the lower wall face
+    assert np.allclose(Fn[ny - 1], -mag, rtol=1e-13, atol=1e-17)  # below the upper face
+    assert np.abs(Fn[3:ny - 1]).max() < 1e-15                # uniform neighbourhoods
     if scheme == "ivd" and par == 1.0:
         assert abs(mag) < 1e-15  # the standard case exerts no wall force
