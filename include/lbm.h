@@ -191,8 +191,12 @@ int lbm_set_wetting(lbm_ctx* ctx, int32_t scheme, double scalar,
  * lbm_get_diagnostics reports as LBM_EDOMAIN.  Clears that flag and the
  * sticky error. */
 int lbm_set_fields(lbm_ctx* ctx, const void* rho_dev, const void* u_dev);
-/* Raw state: f_dev holds Q*N reals ([Q][N]), copied in (checkpoint
- * restore).  Values on solid nodes are ignored. */
+/* Raw state: f_dev holds Q*N reals ([Q][N]) of post-stream populations,
+ * as lbm_get_fields and lbm_step_ckpt write them (checkpoint restore).
+ * Values on solid nodes are ignored.  D3Q19 contexts keep their state in
+ * pull form internally (each node's slots hold its post-collision
+ * populations, and a wall slot holds its fluid neighbour's bounce-back);
+ * this call and lbm_get_fields convert. */
 int lbm_set_state(lbm_ctx* ctx, const void* f_dev);
 
 /* --------------------------------------------------------------- steps */
@@ -204,7 +208,8 @@ int lbm_step(lbm_ctx* ctx, int64_t nsteps);
 /* Macroscopic fields of the current state, written stream-ordered to
  * caller device arrays (each may be NULL): rho_dev N reals (fluid: density;
  * wall nodes: their virtual density, 0 under SFI; other solid: 0), u_dev
- * D*N reals ([D][N], 0 on solid), f_dev Q*N reals (the state). */
+ * D*N reals ([D][N], 0 on solid), f_dev Q*N reals (the post-stream
+ * populations, 0 on solid). */
 int lbm_get_fields(lbm_ctx* ctx, void* rho_dev, void* u_dev, void* f_dev);
 
 /* Reductions over the current state; synchronises the context stream.

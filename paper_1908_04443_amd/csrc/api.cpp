@@ -909,21 +909,49 @@ int lbm_set_wetting(lbm_ctx* c, int32_t scheme, double scalar, const void* phi_d
     return LBM_OK;
 }
 
+// A new state has been written in post-stream form (solid slots zero): into
+// f[cur] for D2Q9, into f[cur ^ 1] for D3Q19, which keeps its populations in
+// pull form (each slot holds the population its downwind neighbour gathers;
+// aux.hip).  Convert it and clear the other buffer.
+static int finish_state(lbm_ctx* c) {
+    const int64_t QN = (int64_t)c->Q * c->N;
+    if (c->prec == 4) {
+        if (c->Q == 19) {
+            LBM_HIP(launch_fill<float>((float*)c->f[c->cur], 0.f, QN, c->stream));
+            LBM_HIP(launch_scatter3<float>(c->cls, (const float*)c->f[c->cur ^ 1],
+                                           (float*)c->f[c->cur], c->p.nx, c->p.ny, c->p.nz,
+                                           c->stream));
+        }
+        LBM_HIP(launch_fill<float>((float*)c->f[c->cur ^ 1], 0.f, QN, c->stream));
+    } else {
+        if (c->Q == 19) {
+            LBM_HIP(launch_fill<double>((double*)c->f[c->cur], 0.0, QN, c->stream));
+            LBM_HIP(launch_scatter3<double>(c->cls, (const double*)c->f[c->cur ^ 1],
+                                            (double*)c->f[c->cur], c->p.nx, c->p.ny, c->p.nz,
+                                            c->stream));
+        }
+        LBM_HIP(launch_fill<double>((double*)c->f[c->cur ^ 1], 0.0, QN, c->stream));
+    }
+    return LBM_OK;
+}
+
 int lbm_set_fields(lbm_ctx* c, const void* rho_dev, const void* u_dev) {
     if (!c || !rho_dev) return fail(LBM_EINVAL, "NULL argument");
     if (c->is_batch) return fail(LBM_EINVAL, "multi-case context: use the _case call");
     if (!c->have_geom) return fail(LBM_ESTATE, "set the geometry before the fields");
     const int64_t QN = (int64_t)c->Q * c->N;
+    // D3Q19: equilibrium into the spare buffer, then into the pull form
+    const int dst = c->Q == 19 ? c->cur ^ 1 : c->cur;
     if (c->prec == 4) {
         LBM_HIP(launch_init_eq<float>(c->Q, c->cls, (const float*)rho_dev, (const float*)u_dev,
-                                      (float*)c->f[c->cur], c->N, c->stream));
-        LBM_HIP(launch_fill<float>((float*)c->f[c->cur ^ 1], 0.f, QN, c->stream));
+                                      (float*)c->f[dst], c->N, c->stream));
     } else {
         LBM_HIP(launch_init_eq<double>(c->Q, c->cls, (const double*)rho_dev,
-                                       (const double*)u_dev, (double*)c->f[c->cur], c->N,
+                                       (const double*)u_dev, (double*)c->f[dst], c->N,
                                        c->stream));
-        LBM_HIP(launch_fill<double>((double*)c->f[c->cur ^ 1], 0.0, QN, c->stream));
     }
+    int rc = finish_state(c);
+    if (rc != LBM_OK) return rc;
     LBM_HIP(launch_fill_i32(c->flag, 0, 4, c->stream));
     c->have_fields = true;
     c->domain_error = false;
@@ -935,15 +963,15 @@ int lbm_set_state(lbm_ctx* c, const void* f_dev) {
     if (c->is_batch) return fail(LBM_EINVAL, "multi-case context: use the _case call");
     if (!c->have_geom) return fail(LBM_ESTATE, "set the geometry before the state");
     const int64_t QN = (int64_t)c->Q * c->N;
-    LBM_HIP(hipMemcpyAsync(c->f[c->cur], f_dev, (size_t)QN * c->prec, hipMemcpyDeviceToDevice,
+    const int dst = c->Q == 19 ? c->cur ^ 1 : c->cur;
+    LBM_HIP(hipMemcpyAsync(c->f[dst], f_dev, (size_t)QN * c->prec, hipMemcpyDeviceToDevice,
                            c->stream));
-    if (c->prec == 4) {
-        LBM_HIP(launch_mask_solid<float>(c->Q, c->cls, (float*)c->f[c->cur], c->N, c->stream));
-        LBM_HIP(launch_fill<float>((float*)c->f[c->cur ^ 1], 0.f, QN, c->stream));
-    } else {
-        LBM_HIP(launch_mask_solid<double>(c->Q, c->cls, (double*)c->f[c->cur], c->N, c->stream));
-        LBM_HIP(launch_fill<double>((double*)c->f[c->cur ^ 1], 0.0, QN, c->stream));
-    }
+    if (c->prec == 4)
+        LBM_HIP(launch_mask_solid<float>(c->Q, c->cls, (float*)c->f[dst], c->N, c->stream));
+    else
+        LBM_HIP(launch_mask_solid<double>(c->Q, c->cls, (double*)c->f[dst], c->N, c->stream));
+    int rc = finish_state(c);
+    if (rc != LBM_OK) return rc;
     LBM_HIP(launch_fill_i32(c->flag, 0, 4, c->stream));
     c->have_fields = true;
     c->domain_error = false;
@@ -983,9 +1011,17 @@ int lbm_get_fields(lbm_ctx* c, void* rho_dev, void* u_dev, void* f_dev) {
                                                     (double*)u_dev, nullptr);
         if (rc != LBM_OK) return rc;
     }
-    if (f_dev)
+    if (f_dev && c->Q == 19) {
+        if (c->prec == 4)
+            LBM_HIP(launch_gather3<float>(c->cls, (const float*)c->f[c->cur], (float*)f_dev,
+                                          c->p.nx, c->p.ny, c->p.nz, c->stream));
+        else
+            LBM_HIP(launch_gather3<double>(c->cls, (const double*)c->f[c->cur], (double*)f_dev,
+                                           c->p.nx, c->p.ny, c->p.nz, c->stream));
+    } else if (f_dev) {
         LBM_HIP(hipMemcpyAsync(f_dev, c->f[c->cur], (size_t)c->Q * c->N * c->prec,
                                hipMemcpyDeviceToDevice, c->stream));
+    }
     return LBM_OK;
 }
 
@@ -1352,8 +1388,16 @@ int lbm_step_ckpt(lbm_ctx* c, int64_t T, int64_t K, void* ckpt_dev) {
     if (c->domain_error) return fail(LBM_EDOMAIN, "a previous step left the psi domain");
     const size_t state = (size_t)c->Q * c->N * c->prec;
     for (int64_t t = 0, sg = 0; t < T; t += K, ++sg) {
-        LBM_HIP(hipMemcpyAsync((char*)ckpt_dev + (size_t)sg * state, c->f[c->cur], state,
-                               hipMemcpyDeviceToDevice, c->stream));
+        // checkpoints hold post-stream populations, as lbm_get_fields writes them
+        char* dst = (char*)ckpt_dev + (size_t)sg * state;
+        if (c->Q == 19 && c->prec == 4)
+            LBM_HIP(launch_gather3<float>(c->cls, (const float*)c->f[c->cur], (float*)dst, c->p.nx,
+                                          c->p.ny, c->p.nz, c->stream));
+        else if (c->Q == 19)
+            LBM_HIP(launch_gather3<double>(c->cls, (const double*)c->f[c->cur], (double*)dst,
+                                           c->p.nx, c->p.ny, c->p.nz, c->stream));
+        else
+            LBM_HIP(hipMemcpyAsync(dst, c->f[c->cur], state, hipMemcpyDeviceToDevice, c->stream));
         const int64_t n = (T - t) < K ? (T - t) : K;
         int rc = c->prec == 4 ? run_steps<float>(c, n) : run_steps<double>(c, n);
         if (rc != LBM_OK) return rc;

@@ -28,6 +28,46 @@ __global__ void k_mask_solid(int Q, const uint8_t* __restrict__ cls, real* __res
     for (int a = 0; a < Q; ++a) f[a * N + n] = real(0);
 }
 
+// D3Q19 contexts keep their populations in pull form: slot a of node y holds
+// the post-collision population that node y + e_a gathers in the next
+// streaming (Eq. 3), and slot a of a non-fluid node y holds the bounce-back
+// of its fluid neighbour y + e_a (halfway bounce-back, Fig. 3).  A
+// post-stream field f then reads f_a(x) = slot_a(x - e_a) at every fluid x,
+// with periodic wrap.
+__device__ __forceinline__ int64_t src3(int x, int y, int z, int a, int nx, int ny, int nz) {
+    int sx = x - D3Q19::ex[a], sy = y - D3Q19::ey[a], sz = z - D3Q19::ez[a];
+    sx = sx < 0 ? sx + nx : (sx >= nx ? sx - nx : sx);
+    sy = sy < 0 ? sy + ny : (sy >= ny ? sy - ny : sy);
+    sz = sz < 0 ? sz + nz : (sz >= nz ? sz - nz : sz);
+    return ((int64_t)sz * ny + sy) * nx + sx;
+}
+
+// post-stream f (Q x N) -> pull form; dst is cleared beforehand
+template <typename real>
+__global__ void k_scatter3(const uint8_t* __restrict__ cls, const real* __restrict__ f,
+                           real* __restrict__ dst, int nx, int ny, int nz) {
+    const int64_t N = (int64_t)nx * ny * nz;
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N || cls[n] != CLS_FLUID) return;
+    const int x = (int)(n % nx), y = (int)((n / nx) % ny), z = (int)(n / ((int64_t)nx * ny));
+#pragma unroll
+    for (int a = 0; a < 19; ++a) dst[a * N + src3(x, y, z, a, nx, ny, nz)] = f[a * N + n];
+}
+
+// pull form -> post-stream f (Q x N), 0 off the fluid
+template <typename real>
+__global__ void k_gather3(const uint8_t* __restrict__ cls, const real* __restrict__ src,
+                          real* __restrict__ f, int nx, int ny, int nz) {
+    const int64_t N = (int64_t)nx * ny * nz;
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    const bool fluid = cls[n] == CLS_FLUID;
+    const int x = (int)(n % nx), y = (int)((n / nx) % ny), z = (int)(n / ((int64_t)nx * ny));
+#pragma unroll
+    for (int a = 0; a < 19; ++a)
+        f[a * N + n] = fluid ? src[a * N + src3(x, y, z, a, nx, ny, nz)] : real(0);
+}
+
 template <typename T>
 __global__ void k_fill(T* p, T v, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -124,6 +164,24 @@ hipError_t launch_init_eq(int lattice, const uint8_t* cls, const real* rho, cons
 }
 
 template <typename real>
+hipError_t launch_scatter3(const uint8_t* cls, const real* f, real* dst, int nx, int ny, int nz,
+                           hipStream_t s) {
+    const int64_t N = (int64_t)nx * ny * nz;
+    hipLaunchKernelGGL((k_scatter3<real>), dim3(nblk(N, 256)), dim3(256), 0, s, cls, f, dst, nx,
+                       ny, nz);
+    return hipGetLastError();
+}
+
+template <typename real>
+hipError_t launch_gather3(const uint8_t* cls, const real* src, real* f, int nx, int ny, int nz,
+                          hipStream_t s) {
+    const int64_t N = (int64_t)nx * ny * nz;
+    hipLaunchKernelGGL((k_gather3<real>), dim3(nblk(N, 256)), dim3(256), 0, s, cls, src, f, nx,
+                       ny, nz);
+    return hipGetLastError();
+}
+
+template <typename real>
 hipError_t launch_mask_solid(int Q, const uint8_t* cls, real* f, int64_t N, hipStream_t s) {
     hipLaunchKernelGGL((k_mask_solid<real>), dim3(nblk(N, 256)), dim3(256), 0, s, Q, cls, f, N);
     return hipGetLastError();
@@ -151,6 +209,14 @@ template hipError_t launch_init_eq<float>(int, const uint8_t*, const float*, con
                                           int64_t, hipStream_t);
 template hipError_t launch_init_eq<double>(int, const uint8_t*, const double*, const double*,
                                            double*, int64_t, hipStream_t);
+template hipError_t launch_scatter3<float>(const uint8_t*, const float*, float*, int, int, int,
+                                           hipStream_t);
+template hipError_t launch_scatter3<double>(const uint8_t*, const double*, double*, int, int, int,
+                                            hipStream_t);
+template hipError_t launch_gather3<float>(const uint8_t*, const float*, float*, int, int, int,
+                                          hipStream_t);
+template hipError_t launch_gather3<double>(const uint8_t*, const double*, double*, int, int, int,
+                                           hipStream_t);
 template hipError_t launch_mask_solid<float>(int, const uint8_t*, float*, int64_t, hipStream_t);
 template hipError_t launch_mask_solid<double>(int, const uint8_t*, double*, int64_t, hipStream_t);
 template hipError_t launch_fill<float>(float*, float, int64_t, hipStream_t);

@@ -161,6 +161,13 @@ hipError_t launch_init_eq(int lattice, const uint8_t* cls, const real* rho, cons
                           real* f, int64_t N, hipStream_t s);
 template <typename real>
 hipError_t launch_mask_solid(int Q, const uint8_t* cls, real* f, int64_t N, hipStream_t s);
+// D3Q19 pull form: post-stream f -> pull form (dst cleared first), and back
+template <typename real>
+hipError_t launch_scatter3(const uint8_t* cls, const real* f, real* dst, int nx, int ny, int nz,
+                           hipStream_t s);
+template <typename real>
+hipError_t launch_gather3(const uint8_t* cls, const real* src, real* f, int nx, int ny, int nz,
+                          hipStream_t s);
 template <typename real>
 hipError_t launch_fill(real* p, real v, int64_t n, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);

@@ -3,7 +3,8 @@
 //
 // Same arithmetic as the tiled 2-D step (Sec. II A, Sec. III B: density,
 // psi, wall virtual density, force, velocity, MRT collision with the Eq. 7
-// forcing, push streaming with halfway bounce-back).  A workgroup owns a
+// forcing, streaming with halfway bounce-back; push for D2Q9, gather from a
+// pull-form state for D3Q19, below).  A workgroup owns a
 // TX x TY column of the cross-section (TY = 1 in 2-D) and a chunk of TZ
 // slices along the sweep axis.  It walks the chunk plus two halo slices on
 // each side; for each slice it
@@ -36,27 +37,59 @@
 
 namespace lbm {
 
+// D3Q19 populations are kept in pull form: the step stores each node's
+// post-collision populations in the node's own slots (whole cache lines per
+// workgroup) and the next step gathers f_a(x) from slot a of x - e_a
+// (Eq. 3).  Halfway bounce-back (Fig. 3) is folded into the store: a fluid
+// node whose neighbour x + e_a is not fluid also writes its f*_a into slot
+// opp(a) of that neighbour, which is exactly where the gather of direction
+// opp(a) at x looks.  No non-fluid node gathers, so those slots are free.
+// D2Q9 keeps the push form (the post-stream populations).
+
+// node index of x - e_a for a node (x, y, z) inside the lattice, periodic
+template <typename L>
+__device__ __forceinline__ uint32_t up_node(int a, int x, int y, int z, int na, int nb, int nc,
+                                            uint32_t nab) {
+    int sx = x - L::ex[a], sy = y - L::ey[a], sz = z - L::ez[a];
+    sx = sx < 0 ? sx + na : (sx >= na ? sx - na : sx);
+    sy = sy < 0 ? sy + nb : (sy >= nb ? sy - nb : sy);
+    sz = sz < 0 ? sz + nc : (sz >= nc ? sz - nc : sz);
+    return (uint32_t)sz * nab + (uint32_t)sy * (uint32_t)na + (uint32_t)sx;
+}
+
 // Density of every node (Eq. 4), summed in velocity order; 0 off the fluid.
-template <int Q, typename real>
+// D2Q9: from the post-stream populations of the node; D3Q19: gathered from
+// the pull form.
+template <typename L, typename real>
 __global__ __launch_bounds__(256) void k_density(const uint8_t* __restrict__ cls,
                                                  const real* __restrict__ f, real* __restrict__ rho,
-                                                 uint32_t N) {
+                                                 int na, int nb, int nc) {
+    constexpr int Q = L::Q;
+    const uint32_t nab = (uint32_t)na * (uint32_t)nb, N = nab * (uint32_t)nc;
     const uint32_t n = blockIdx.x * 256u + threadIdx.x;
     if (n >= N) return;
     real r = real(0);
     if (cls[n] == CLS_FLUID) {
-        r = f[n];
+        if constexpr (L::D == 3) {
+            const int x = (int)(n % (uint32_t)na), y = (int)((n / (uint32_t)na) % (uint32_t)nb);
+            const int z = (int)(n / nab);
+            r = f[n];
 #pragma unroll
-        for (int a = 1; a < Q; ++a) r += f[(size_t)a * N + n];
+            for (int a = 1; a < Q; ++a) r += f[(size_t)a * N + up_node<L>(a, x, y, z, na, nb, nc, nab)];
+        } else {
+            r = f[n];
+#pragma unroll
+            for (int a = 1; a < Q; ++a) r += f[(size_t)a * N + n];
+        }
     }
     rho[n] = r;
 }
 
-template <int Q, typename real>
+template <typename L, typename real>
 static void launch_density(const Coef<real>& C, const Fields<real>& F, hipStream_t s) {
     const uint32_t N = (uint32_t)C.nx * (uint32_t)C.ny * (uint32_t)C.nz;
-    hipLaunchKernelGGL((k_density<Q, real>), dim3((N + 255) / 256), dim3(256), 0, s, F.cls, F.fin,
-                       F.rho, N);
+    hipLaunchKernelGGL((k_density<L, real>), dim3((N + 255) / 256), dim3(256), 0, s, F.cls, F.fin,
+                       F.rho, C.nx, C.ny, C.nz);
 }
 
 // FUSED: no density pass.  Phase A loads the populations of its slice,
@@ -70,12 +103,14 @@ template <typename L, typename real, int TX, int TY, int TZ, int MODE, bool XCD,
 __global__ __launch_bounds__(TX* TY, OCC) void k_step_march(Coef<real> C, Fields<real> Fd,
                                                             FieldOut<real> Out) {
     constexpr bool D3 = (L::D == 3);
+    constexpr bool PULL = D3;                // populations in pull form (D3Q19)
     constexpr int Q = L::Q;
     constexpr int NT = TX * TY;
     constexpr int HB = D3 ? 2 : 0;           // halo along the second tile axis
     constexpr int PA = TX + 4, PB = TY + 2 * HB, PS = PA * PB;
     constexpr int RING = PS - TX * TY;
-    static_assert(RING <= NT, "each thread handles at most one halo position");
+    constexpr int JR = (RING + NT - 1) / NT;  // halo positions per thread
+    static_assert(!FUSED || JR == 1, "the fused sweep keeps one halo position per thread");
     constexpr int NSLOT = 5, NPSI = 4;
 
     __shared__ uint8_t s_cls[NSLOT][PS];
@@ -96,39 +131,44 @@ __global__ __launch_bounds__(TX* TY, OCC) void k_step_march(Coef<real> C, Fields
     const int bz = bid / (gridDim.x * gridDim.y);
     const int a0 = bx * TX, b0 = by * TY, c0 = bz * TZ;
 
-    // owned position of this thread and its halo position (if any)
+    // owned position of this thread
     const int own_la = 2 + tid % TX, own_lb = HB + tid / TX;
-    int ring_la = -1, ring_lb = -1;
-    if (tid < RING) {
-        // enumerate the plane positions outside the owned TX x TY block
-        int cnt = 0;
-        if (D3) {
-            // two full rows below and above, then two columns on each side
-            if (tid < 2 * PA) {
-                ring_lb = tid / PA;
-                ring_la = tid % PA;
-            } else if (tid < 4 * PA) {
-                ring_lb = TY + 2 + (tid - 2 * PA) / PA;
-                ring_la = (tid - 2 * PA) % PA;
-            } else {
-                const int j = tid - 4 * PA;
-                ring_lb = 2 + j / 4;
-                const int c = j % 4;
-                ring_la = c < 2 ? c : TX + c;
-            }
-        } else {
-            ring_lb = 0;
-            ring_la = tid < 2 ? tid : TX + tid;
-        }
-        (void)cnt;
-    }
     const int own_a = a0 + own_la - 2, own_b = b0 + own_lb - HB;
     const bool own_in = own_a < na && own_b < nb;  // ragged tiles
     const uint32_t own_ab = (uint32_t)wrapi(own_b, nb) * na + wrapi(own_a, na);
-    uint32_t ring_ab = 0;
-    if (tid < RING) ring_ab = (uint32_t)wrapi(b0 + ring_lb - HB, nb) * na + wrapi(a0 + ring_la - 2, na);
     const int own_p = own_lb * PA + own_la;
-    const int ring_p = (tid < RING) ? ring_lb * PA + ring_la : 0;
+    // halo positions j = tid, tid + NT, ... (j < RING) of the plane outside
+    // the owned TX x TY block: in 3-D two full rows below and above, then two
+    // columns on each side; in 2-D two nodes on each side
+    const int own_aw = wrapi(own_a, na), own_bw = D3 ? wrapi(own_b, nb) : 0;
+    int ring_p[JR], ring_x[JR], ring_y[JR];
+    uint32_t ring_ab[JR];
+#pragma unroll
+    for (int jj = 0; jj < JR; ++jj) {
+        const int j = tid + jj * NT;
+        int la = 0, lb = 0;
+        if (D3) {
+            if (j < 2 * PA) {
+                lb = j / PA;
+                la = j % PA;
+            } else if (j < 4 * PA) {
+                lb = TY + 2 + (j - 2 * PA) / PA;
+                la = (j - 2 * PA) % PA;
+            } else {
+                const int k = j - 4 * PA;
+                lb = 2 + k / 4;
+                const int c = k % 4;
+                la = c < 2 ? c : TX + c;
+            }
+        } else {
+            la = j < 2 ? j : TX + j;
+        }
+        const bool in = j < RING;
+        ring_p[jj] = in ? lb * PA + la : 0;
+        ring_x[jj] = in ? wrapi(a0 + la - 2, na) : 0;
+        ring_y[jj] = in ? wrapi(b0 + lb - HB, nb) : 0;
+        ring_ab[jj] = (uint32_t)ring_y[jj] * na + ring_x[jj];
+    }
 
     bool bad = false;
     double d_sum = 0.0;
@@ -147,14 +187,18 @@ __global__ __launch_bounds__(TX* TY, OCC) void k_step_march(Coef<real> C, Fields
                 // density of each node in velocity order, 0 off the fluid
                 const uint8_t oc = Fd.cls[base + own_ab];
 #pragma unroll
-                for (int a = 0; a < Q; ++a) Rl[a] = io.ld(a, base + own_ab);
+                for (int a = 0; a < Q; ++a)
+                    Rl[a] = io.ld(a, PULL ? up_node<L>(a, own_aw, own_bw, cz, na, nb, nc, nab)
+                                          : base + own_ab);
                 uint8_t rc = CLS_SOLID;
                 real rr = real(0);
                 if (tid < RING) {
-                    rc = Fd.cls[base + ring_ab];
-                    rr = io.ld(0, base + ring_ab);
+                    rc = Fd.cls[base + ring_ab[0]];
+                    rr = io.ld(0, base + ring_ab[0]);
 #pragma unroll
-                    for (int a = 1; a < Q; ++a) rr += io.ld(a, base + ring_ab);
+                    for (int a = 1; a < Q; ++a)
+                        rr += io.ld(a, PULL ? up_node<L>(a, ring_x[0], ring_y[0], cz, na, nb, nc, nab)
+                                            : base + ring_ab[0]);
                 }
                 real r = Rl[0];
 #pragma unroll
@@ -162,16 +206,19 @@ __global__ __launch_bounds__(TX* TY, OCC) void k_step_march(Coef<real> C, Fields
                 s_cls[slot][own_p] = oc;
                 s_rho[slot][own_p] = oc == CLS_FLUID ? r : real(0);
                 if (tid < RING) {
-                    s_cls[slot][ring_p] = rc;
-                    s_rho[slot][ring_p] = rc == CLS_FLUID ? rr : real(0);
+                    s_cls[slot][ring_p[0]] = rc;
+                    s_rho[slot][ring_p[0]] = rc == CLS_FLUID ? rr : real(0);
                 }
             } else {
                 // densities come from the density pass: one value per node
                 s_cls[slot][own_p] = Fd.cls[base + own_ab];
                 s_rho[slot][own_p] = Fd.rho[base + own_ab];
-                if (tid < RING) {
-                    s_cls[slot][ring_p] = Fd.cls[base + ring_ab];
-                    s_rho[slot][ring_p] = Fd.rho[base + ring_ab];
+#pragma unroll
+                for (int jj = 0; jj < JR; ++jj) {
+                    if (tid + jj * NT < RING) {
+                        s_cls[slot][ring_p[jj]] = Fd.cls[base + ring_ab[jj]];
+                        s_rho[slot][ring_p[jj]] = Fd.rho[base + ring_ab[jj]];
+                    }
                 }
             }
         }
@@ -283,7 +330,9 @@ __global__ __launch_bounds__(TX* TY, OCC) void k_step_march(Coef<real> C, Fields
                 }
                 real fl[Q];
 #pragma unroll
-                for (int a = 0; a < Q; ++a) fl[a] = FUSED ? Rc[a] : io.ld(a, n);
+                for (int a = 0; a < Q; ++a)
+                    fl[a] = FUSED ? Rc[a]
+                                  : io.ld(a, PULL ? up_node<L>(a, own_a, own_b, cc, na, nb, nc, nab) : n);
                 if (MODE == MODE_FIELDS) {
                     real j[3] = {real(0), real(0), real(0)};
 #pragma unroll
@@ -320,12 +369,18 @@ __global__ __launch_bounds__(TX* TY, OCC) void k_step_march(Coef<real> C, Fields
                         const int ec = D3 ? L::ez[a] : L::ey[a];
                         const int s3 = (it - 2 + ec + NSLOT) % NSLOT;
                         const int q = own_p + ea + eb * PA;
-                        if (s_cls[s3][q] == CLS_FLUID) {
-                            int ta = ga + ea, tb = gb + eb, tc = cc + ec;
-                            ta = ta < 0 ? ta + na : (ta >= na ? ta - na : ta);
-                            tb = tb < 0 ? tb + nb : (tb >= nb ? tb - nb : tb);
-                            tc = tc < 0 ? tc + nc : (tc >= nc ? tc - nc : tc);
-                            io.st(a, (uint32_t)tc * nab + (uint32_t)tb * na + ta, fs[a]);
+                        const bool fluid_to = s_cls[s3][q] == CLS_FLUID;
+                        int ta = ga + ea, tb = gb + eb, tc = cc + ec;
+                        ta = ta < 0 ? ta + na : (ta >= na ? ta - na : ta);
+                        tb = tb < 0 ? tb + nb : (tb >= nb ? tb - nb : tb);
+                        tc = tc < 0 ? tc + nc : (tc >= nc ? tc - nc : tc);
+                        const uint32_t t = (uint32_t)tc * nab + (uint32_t)tb * na + ta;
+                        if constexpr (PULL) {
+                            // own slot; a wall neighbour also gets the bounce-back
+                            io.st(a, n, fs[a]);
+                            if (!fluid_to) io.st(L::opp[a], t, fs[a]);
+                        } else if (fluid_to) {
+                            io.st(a, t, fs[a]);
                         } else {
                             io.st(L::opp[a], n, fs[a]);
                         }
@@ -360,7 +415,7 @@ __global__ __launch_bounds__(TX* TY, OCC) void k_step_march(Coef<real> C, Fields
 // 2-node halo in every direction (one value per node, mostly from L2) and
 // each thread's TZ owned nodes' populations into registers; psi (with the
 // wall virtual densities) follows on the brick plus a 1-node halo, then the
-// owned nodes collide and push.  Two barriers per brick and no dependent
+// owned nodes collide and store (pull form).  Two barriers per brick and no dependent
 // chain along z, so many independent workgroups hide the memory latency.
 // Step mode only (the field/diagnostic pass uses the sweep).
 template <typename real, int TX, int TY, int TZ, bool XCD>
@@ -390,12 +445,13 @@ __global__ __launch_bounds__(TX* TY) void k_step_brick(Coef<real> C, Fields<real
     const int ga = a0 + tx, gb = b0 + ty;
     const bool own_xy = ga < na && gb < nb;
     const uint32_t own_ab = (uint32_t)wrapi(gb, nb) * na + wrapi(ga, na);
+    const int gaw = wrapi(ga, na), gbw = wrapi(gb, nb);
     real f[TZ][Q];
 #pragma unroll
     for (int k = 0; k < TZ; ++k) {
-        const uint32_t n = (uint32_t)wrapi(c0 + k, nc) * nab + own_ab;
+        const int gcw = wrapi(c0 + k, nc);
 #pragma unroll
-        for (int a = 0; a < Q; ++a) f[k][a] = io.ld(a, n);
+        for (int a = 0; a < Q; ++a) f[k][a] = io.ld(a, up_node<L>(a, gaw, gbw, gcw, na, nb, nc, nab));
     }
     constexpr int JB = (PS + NT - 1) / NT;
     uint8_t hc[JB];
@@ -463,7 +519,7 @@ __global__ __launch_bounds__(TX* TY) void k_step_brick(Coef<real> C, Fields<real
     }
     __syncthreads();
 
-    // ---- owned nodes: force (Eq. 5, Eq. 8), collision, push with bounce-back
+    // ---- owned nodes: force (Eq. 5, Eq. 8), collision, pull-form store
 #pragma unroll
     for (int k = 0; k < TZ; ++k) {
         const int gc = c0 + k;
@@ -505,15 +561,15 @@ __global__ __launch_bounds__(TX* TY) void k_step_brick(Coef<real> C, Fields<real
         collide<L, real>(C, f[k], rho, F, Fm, psi_c, fs, u);
 #pragma unroll
         for (int a = 0; a < Q; ++a) {
+            // pull form: own slot; a wall neighbour also gets the bounce-back
+            io.st(a, n, fs[a]);
             const int q = p + L::ex[a] + L::ey[a] * PX + L::ez[a] * PXY;
-            if (s_cls[q] == CLS_FLUID) {
+            if (s_cls[q] != CLS_FLUID) {
                 int ta = ga + L::ex[a], tb = gb + L::ey[a], tc = gc + L::ez[a];
                 ta = ta < 0 ? ta + na : (ta >= na ? ta - na : ta);
                 tb = tb < 0 ? tb + nb : (tb >= nb ? tb - nb : tb);
                 tc = tc < 0 ? tc + nc : (tc >= nc ? tc - nc : tc);
-                io.st(a, (uint32_t)tc * nab + (uint32_t)tb * na + ta, fs[a]);
-            } else {
-                io.st(L::opp[a], n, fs[a]);
+                io.st(L::opp[a], (uint32_t)tc * nab + (uint32_t)tb * na + ta, fs[a]);
             }
         }
     }
@@ -535,13 +591,14 @@ template <typename real>
 struct Variants3D;
 template <>
 struct Variants3D<float> {
-    static constexpr int count = 8;
+    static constexpr int count = 10;
     static constexpr int preferred = 2;  // 32 x 8 cross-section, chunks of 8 slices
     static constexpr Shape3D shape[count] = {
         {32, 8, 16, true, false, 1, false}, {32, 8, 16, false, false, 1, false},
         {32, 8, 8, true, false, 1, false},  {32, 8, 32, true, false, 1, false},
         {16, 16, 16, true, false, 1, false}, {32, 8, 16, true, true, 1, false},
-        {32, 8, 32, true, true, 1, false},  {32, 8, 2, true, false, 1, true}};
+        {32, 8, 32, true, true, 1, false},  {32, 8, 2, true, false, 1, true},
+        {64, 4, 16, true, false, 1, false}, {256, 2, 16, true, false, 1, false}};
 };
 template <>
 struct Variants3D<double> {
@@ -597,17 +654,17 @@ hipError_t launch_step3d(const Coef<real>& C, const Fields<real>& F, const Field
     if (variant < 0 || variant >= Variants3D<real>::count) return hipErrorInvalidValue;
     // population arrays of 4 GiB or more cannot use 32-bit buffer offsets
     if ((uint64_t)19 * (uint64_t)C.nx * C.ny * C.nz * sizeof(real) > 0xFFFFFFFFull) {
-        launch_density<19, real>(C, F, s);
+        launch_density<D3Q19, real>(C, F, s);
         if (mode == MODE_STEP) launch_v3<real, 0, MODE_STEP, false>(C, F, O, s);
         else launch_v3<real, 0, MODE_FIELDS, false>(C, F, O, s);
         return hipGetLastError();
     }
     if (mode == MODE_FIELDS) {
-        launch_density<19, real>(C, F, s);
+        launch_density<D3Q19, real>(C, F, s);
         launch_v3<real, 0, MODE_FIELDS>(C, F, O, s);
         return hipGetLastError();
     }
-    if (!Variants3D<real>::shape[variant].fused) launch_density<19, real>(C, F, s);
+    if (!Variants3D<real>::shape[variant].fused) launch_density<D3Q19, real>(C, F, s);
     static const auto tab = table_v3<real>(std::make_index_sequence<Variants3D<real>::count>{});
     tab[variant](C, F, O, s);
     return hipGetLastError();
@@ -648,7 +705,7 @@ static void launch_v2m(const Coef<real>& C, const Fields<real>& F, const FieldOu
 template <typename real>
 hipError_t launch_step2d_march(const Coef<real>& C, const Fields<real>& F, const FieldOut<real>& O,
                                int idx, hipStream_t s) {
-    launch_density<9, real>(C, F, s);
+    launch_density<D2Q9, real>(C, F, s);
     if (idx == 0) launch_v2m<real, 0, MODE_STEP>(C, F, O, s);
     else if constexpr (Variants2M<real>::count > 1) {
         if (idx == 1) launch_v2m<real, 1, MODE_STEP>(C, F, O, s);
