@@ -61,7 +61,8 @@ enum { LBM_WET_IVD = 0, LBM_WET_VD = 1, LBM_WET_SFI = 2, LBM_WET_GF = 3 };
 /* Model parameters, copied at create.
  *  lattice     9 (D2Q9) or 19 (D3Q19)
  *  precision   4 (float) or 8 (double)
- *  nx, ny, nz  lattice size (nz = 1 for D2Q9)
+ *  nx, ny, nz  lattice size (nz = 1 for D2Q9; ny, nz <= 65535 for D3Q19;
+ *              nx*ny*nz <= 4e9)
  *  tau[k]      relaxation time of moment row k (Eq. 2); all > 0.5.  Row
  *              order is that of the relaxation matrix of Eq. 2: D2Q9
  *              (rho, e, eps, jx, qx, jy, qy, pxx, pxy); D3Q19 (rho, e, eps,

@@ -32,6 +32,8 @@ int validate(const lbm_params* p) {
     if (p->precision != 4 && p->precision != 8) return fail(LBM_EINVAL, "precision must be 4 or 8");
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail(LBM_EINVAL, "sizes must be positive");
     if (p->lattice == 9 && p->nz != 1) return fail(LBM_EINVAL, "D2Q9 needs nz == 1");
+    if (p->lattice == 19 && (p->ny > 65535 || p->nz > 65535))
+        return fail(LBM_EINVAL, "D3Q19 needs ny and nz of at most 65535 (launch grid rows)");
     const double N = (double)p->nx * p->ny * p->nz;
     if (N > 4.0e9) return fail(LBM_EINVAL, "lattice too large");
     for (int k = 0; k < p->lattice; ++k)

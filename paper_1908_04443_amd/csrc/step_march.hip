@@ -58,38 +58,46 @@ __device__ __forceinline__ uint32_t up_node(int a, int x, int y, int z, int na, 
 }
 
 // Density of every node (Eq. 4), summed in velocity order; 0 off the fluid.
-// D2Q9: from the post-stream populations of the node; D3Q19: gathered from
-// the pull form.
+// D2Q9: from the post-stream populations of the node (a 1-D grid over the
+// nodes).  D3Q19: gathered from the pull form; blockIdx.y and blockIdx.z
+// give the row and the slice, so the gather needs no index division.
 template <typename L, typename real>
 __global__ __launch_bounds__(256) void k_density(const uint8_t* __restrict__ cls,
                                                  const real* __restrict__ f, real* __restrict__ rho,
                                                  int na, int nb, int nc) {
     constexpr int Q = L::Q;
     const uint32_t nab = (uint32_t)na * (uint32_t)nb, N = nab * (uint32_t)nc;
-    const uint32_t n = blockIdx.x * 256u + threadIdx.x;
-    if (n >= N) return;
-    real r = real(0);
-    if (cls[n] == CLS_FLUID) {
-        if constexpr (L::D == 3) {
-            const int x = (int)(n % (uint32_t)na), y = (int)((n / (uint32_t)na) % (uint32_t)nb);
-            const int z = (int)(n / nab);
+    if constexpr (L::D == 3) {
+        const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
+        if (x >= na) return;
+        const uint32_t n = (uint32_t)z * nab + (uint32_t)y * (uint32_t)na + (uint32_t)x;
+        real r = real(0);
+        if (cls[n] == CLS_FLUID) {
             r = f[n];
 #pragma unroll
             for (int a = 1; a < Q; ++a) r += f[(size_t)a * N + up_node<L>(a, x, y, z, na, nb, nc, nab)];
-        } else {
+        }
+        rho[n] = r;
+    } else {
+        const uint32_t n = blockIdx.x * 256u + threadIdx.x;
+        if (n >= N) return;
+        real r = real(0);
+        if (cls[n] == CLS_FLUID) {
             r = f[n];
 #pragma unroll
             for (int a = 1; a < Q; ++a) r += f[(size_t)a * N + n];
         }
+        rho[n] = r;
     }
-    rho[n] = r;
 }
 
 template <typename L, typename real>
 static void launch_density(const Coef<real>& C, const Fields<real>& F, hipStream_t s) {
     const uint32_t N = (uint32_t)C.nx * (uint32_t)C.ny * (uint32_t)C.nz;
-    hipLaunchKernelGGL((k_density<L, real>), dim3((N + 255) / 256), dim3(256), 0, s, F.cls, F.fin,
-                       F.rho, C.nx, C.ny, C.nz);
+    // the 3-D grid fits: D3Q19 parameters are validated to ny, nz <= 65535
+    const dim3 grid = (L::D == 3) ? dim3((C.nx + 255) / 256, C.ny, C.nz) : dim3((N + 255) / 256);
+    hipLaunchKernelGGL((k_density<L, real>), grid, dim3(256), 0, s, F.cls, F.fin, F.rho, C.nx,
+                       C.ny, C.nz);
 }
 
 // FUSED: no density pass.  Phase A loads the populations of its slice,

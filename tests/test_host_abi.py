@@ -151,3 +151,15 @@ def test_c_program_links_against_the_library(L):
     out = subprocess.run(["ldd", build.DEMO], capture_output=True, text=True, check=True).stdout
     assert "liblbm.so" in out and "libamdhip64" in out
     assert "not found" not in out
+
+
+def test_validate_d3q19_grid_limits(L):
+    """D3Q19 rows and slices index the launch grid: at most 65535 each."""
+    p = _good(L, lattice=19, nx=8, ny=65535, nz=4)
+    assert L.lbm_validate_params(p) == 0
+    p = _good(L, lattice=19, nx=8, ny=65536, nz=4)
+    assert L.lbm_validate_params(p) == L.LBM_EINVAL
+    p = _good(L, lattice=19, nx=8, ny=4, nz=70000)
+    assert L.lbm_validate_params(p) == L.LBM_EINVAL
+    p = _good(L, nx=8, ny=70000)  # D2Q9 rows are not limited
+    assert L.lbm_validate_params(p) == 0
