@@ -126,6 +126,25 @@ def test_d3q19_fp64(oracle_mod, gpu_lib):
     _compare(oracle_mod, s, res, 60, 1e-12, 1e-12)
 
 
+@pytest.mark.parametrize("scheme", ["ivd", "vd", "sfi"])
+def test_d3q19_schemes_fp64(oracle_mod, gpu_lib, scheme):
+    """Every 3-D wetting scheme with the sigma term and a body force, on sizes
+    that leave partial tiles on every axis, with the sphere across the
+    periodic seam in z (bounce-back slots written across the wrap)."""
+    case = dict(lattice=19, nx=41, ny=19, nz=23, T_ratio=0.8, sigma=0.1,
+                body=(1e-6, 0.0, -2e-6),
+                geometry=("disk", (20, 9, 2), 6), init=("droplet", (20, 9, 12), 5),
+                scheme=scheme, rho_w=0.2, G_w=0.05, noise=1e-6, seed=4, precision=8)
+    if scheme == "ivd":
+        rng = np.random.default_rng(6)
+        case["phi_field"] = lambda solid: 1.0 + 0.3 * rng.random(solid.shape)
+        case["drho_field"] = lambda solid: 0.05 * rng.random(solid.shape)
+    s = Setup(oracle_mod, case)
+    res = run_gpu(gpu_lib, s, 60)
+    assert np.array_equal(res["walls"], s.walls)
+    _compare(oracle_mod, s, res, 60, 1e-12, 1e-12)
+
+
 def test_d3q19_fp32(oracle_mod, gpu_lib):
     case = dict(lattice=19, nx=34, ny=17, nz=19, T_ratio=0.8, sigma=0.0,
                 geometry=("disk", (17, 8, 8), 5), init=("droplet", (17, 8, 15), 4),
