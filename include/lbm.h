@@ -291,7 +291,8 @@ int lbm_get_diagnostics_case(lbm_ctx* ctx, int32_t i, lbm_diag* host_out);
  *
  * lbm_step_ckpt: advance T steps like lbm_step, storing the state at times
  * 0, K, 2K, ... (< T) into ckpt_dev (caller-owned device memory of
- * ceil(T/K) * Q*N reals).
+ * ceil(T/K) * Q*N reals), as post-stream populations: each checkpoint is
+ * what lbm_get_fields writes and what lbm_set_state takes.
  *
  * lbm_adjoint: with the checkpoints of that run (taken under the same
  * geometry and wetting parameters), computes

@@ -611,7 +611,7 @@ struct Variants3D<float> {
 template <>
 struct Variants3D<double> {
     static constexpr int count = 4;
-    static constexpr int preferred = 0;
+    static constexpr int preferred = 3;  // the brick: 1.70 ms against 1.81 ms on the 256^3 sphere
     static constexpr Shape3D shape[count] = {
         {32, 8, 16, true, false, 1, false}, {32, 8, 16, false, false, 1, false},
         {32, 8, 16, true, true, 1, false}, {32, 8, 2, true, false, 1, true}};
