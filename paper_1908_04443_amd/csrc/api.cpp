@@ -937,11 +937,24 @@ static int finish_state(lbm_ctx* c) {
     return LBM_OK;
 }
 
+// The current state as post-stream populations (Q x N, 0 on solid) into dst.
+static int read_state(lbm_ctx* c, void* dst) {
+    if (c->Q == 19 && c->prec == 4)
+        LBM_HIP(launch_gather3<float>(c->cls, (const float*)c->f[c->cur], (float*)dst, c->p.nx,
+                                      c->p.ny, c->p.nz, c->stream));
+    else if (c->Q == 19)
+        LBM_HIP(launch_gather3<double>(c->cls, (const double*)c->f[c->cur], (double*)dst, c->p.nx,
+                                       c->p.ny, c->p.nz, c->stream));
+    else
+        LBM_HIP(hipMemcpyAsync(dst, c->f[c->cur], (size_t)c->Q * c->N * c->prec,
+                               hipMemcpyDeviceToDevice, c->stream));
+    return LBM_OK;
+}
+
 int lbm_set_fields(lbm_ctx* c, const void* rho_dev, const void* u_dev) {
     if (!c || !rho_dev) return fail(LBM_EINVAL, "NULL argument");
     if (c->is_batch) return fail(LBM_EINVAL, "multi-case context: use the _case call");
     if (!c->have_geom) return fail(LBM_ESTATE, "set the geometry before the fields");
-    const int64_t QN = (int64_t)c->Q * c->N;
     // D3Q19: equilibrium into the spare buffer, then into the pull form
     const int dst = c->Q == 19 ? c->cur ^ 1 : c->cur;
     if (c->prec == 4) {
@@ -1013,18 +1026,7 @@ int lbm_get_fields(lbm_ctx* c, void* rho_dev, void* u_dev, void* f_dev) {
                                                     (double*)u_dev, nullptr);
         if (rc != LBM_OK) return rc;
     }
-    if (f_dev && c->Q == 19) {
-        if (c->prec == 4)
-            LBM_HIP(launch_gather3<float>(c->cls, (const float*)c->f[c->cur], (float*)f_dev,
-                                          c->p.nx, c->p.ny, c->p.nz, c->stream));
-        else
-            LBM_HIP(launch_gather3<double>(c->cls, (const double*)c->f[c->cur], (double*)f_dev,
-                                           c->p.nx, c->p.ny, c->p.nz, c->stream));
-    } else if (f_dev) {
-        LBM_HIP(hipMemcpyAsync(f_dev, c->f[c->cur], (size_t)c->Q * c->N * c->prec,
-                               hipMemcpyDeviceToDevice, c->stream));
-    }
-    return LBM_OK;
+    return f_dev ? read_state(c, f_dev) : LBM_OK;
 }
 
 int lbm_get_diagnostics(lbm_ctx* c, lbm_diag* out) {
@@ -1391,15 +1393,8 @@ int lbm_step_ckpt(lbm_ctx* c, int64_t T, int64_t K, void* ckpt_dev) {
     const size_t state = (size_t)c->Q * c->N * c->prec;
     for (int64_t t = 0, sg = 0; t < T; t += K, ++sg) {
         // checkpoints hold post-stream populations, as lbm_get_fields writes them
-        char* dst = (char*)ckpt_dev + (size_t)sg * state;
-        if (c->Q == 19 && c->prec == 4)
-            LBM_HIP(launch_gather3<float>(c->cls, (const float*)c->f[c->cur], (float*)dst, c->p.nx,
-                                          c->p.ny, c->p.nz, c->stream));
-        else if (c->Q == 19)
-            LBM_HIP(launch_gather3<double>(c->cls, (const double*)c->f[c->cur], (double*)dst,
-                                           c->p.nx, c->p.ny, c->p.nz, c->stream));
-        else
-            LBM_HIP(hipMemcpyAsync(dst, c->f[c->cur], state, hipMemcpyDeviceToDevice, c->stream));
+        int rc0 = read_state(c, (char*)ckpt_dev + (size_t)sg * state);
+        if (rc0 != LBM_OK) return rc0;
         const int64_t n = (T - t) < K ? (T - t) : K;
         int rc = c->prec == 4 ? run_steps<float>(c, n) : run_steps<double>(c, n);
         if (rc != LBM_OK) return rc;

@@ -12,13 +12,14 @@
 //      2-node halo into slot (it mod 5) of an LDS ring,
 //   B  finishes the wall virtual densities and psi of the previous slice on
 //      the tile plus a 1-node halo (ring of 4 psi slots),
-//   C  collides and streams the slice two behind the load front; its
-//      populations are read again here (two iterations after phase A read
-//      them, so they come from L2) instead of being held in registers,
-//      which keeps the register count low enough for several waves per SIMD.
+//   C  collides and streams the slice two behind the load front, reading
+//      its populations here rather than holding them in registers since
+//      phase A, which keeps the register count low enough for several
+//      waves per SIMD.
 // The densities of phase A come from a separate density pass (k_density,
 // launched just before): the halo then costs one value per node instead
 // of Q populations, and each node's populations are read once, in phase C.
+// (The FUSED variant below sums the densities in phase A instead.)
 // With 19 populations and a 2-node halo around a 32 x 8 cross-section this
 // removes most of the bytes of a 3-D step that sums the halo's
 // populations inside the sweep.
