@@ -167,15 +167,18 @@ __device__ __forceinline__ real buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, 
         return __builtin_bit_cast(real, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
 }
 
-template <typename real>
+// AUX is the cache policy of the store: 0 normal, ST_NT non-temporal (the
+// gfx950 "nt" bit: the line is not kept in the caches for reuse).
+constexpr int ST_NT = 2;
+template <typename real, int AUX = 0>
 __device__ __forceinline__ void buf_st(real v, __amdgpu_buffer_rsrc_t r, uint32_t voff,
                                        uint32_t soff) {
     if constexpr (sizeof(real) == 4)
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, (int)soff, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, (int)soff, AUX);
     else
     {
         typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)voff, (int)soff, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)voff, (int)soff, AUX);
     }
 }
 
@@ -201,6 +204,14 @@ struct PopIO {
     __device__ __forceinline__ void st(int a, uint32_t n, real v) const {
         if constexpr (BUF) buf_st<real>(v, rout, n * (uint32_t)sizeof(real), (uint32_t)a * N * (uint32_t)sizeof(real));
         else fout[(size_t)a * N + n] = v;
+    }
+    // the same with a non-temporal store: for stores that fill whole cache
+    // lines of one workgroup (the pull form's own slots).  Partly written
+    // lines, as in a push, must merge in L2 and are slower this way.
+    __device__ __forceinline__ void st_nt(int a, uint32_t n, real v) const {
+        if constexpr (BUF)
+            buf_st<real, ST_NT>(v, rout, n * (uint32_t)sizeof(real), (uint32_t)a * N * (uint32_t)sizeof(real));
+        else __builtin_nontemporal_store(v, &fout[(size_t)a * N + n]);
     }
     // push with halfway bounce-back in one store: to slot a of node
     // n + delta if `stream`, else to slot b of node n (delta uniform across

@@ -386,7 +386,7 @@ __global__ __launch_bounds__(TX* TY, OCC) void k_step_march(Coef<real> C, Fields
                         const uint32_t t = (uint32_t)tc * nab + (uint32_t)tb * na + ta;
                         if constexpr (PULL) {
                             // own slot; a wall neighbour also gets the bounce-back
-                            io.st(a, n, fs[a]);
+                            io.st_nt(a, n, fs[a]);
                             if (!fluid_to) io.st(L::opp[a], t, fs[a]);
                         } else if (fluid_to) {
                             io.st(a, t, fs[a]);
@@ -571,7 +571,7 @@ __global__ __launch_bounds__(TX* TY) void k_step_brick(Coef<real> C, Fields<real
 #pragma unroll
         for (int a = 0; a < Q; ++a) {
             // pull form: own slot; a wall neighbour also gets the bounce-back
-            io.st(a, n, fs[a]);
+            io.st_nt(a, n, fs[a]);
             const int q = p + L::ex[a] + L::ey[a] * PX + L::ez[a] * PXY;
             if (s_cls[q] != CLS_FLUID) {
                 int ta = ga + L::ex[a], tb = gb + L::ey[a], tc = gc + L::ez[a];
@@ -612,7 +612,7 @@ struct Variants3D<float> {
 template <>
 struct Variants3D<double> {
     static constexpr int count = 4;
-    static constexpr int preferred = 3;  // the brick: 1.70 ms against 1.81 ms on the 256^3 sphere
+    static constexpr int preferred = 3;  // the brick: 1.63 ms against 1.76 ms on the 256^3 sphere
     static constexpr Shape3D shape[count] = {
         {32, 8, 16, true, false, 1, false}, {32, 8, 16, false, false, 1, false},
         {32, 8, 16, true, true, 1, false}, {32, 8, 2, true, false, 1, true}};
