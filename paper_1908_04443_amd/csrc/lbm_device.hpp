@@ -219,14 +219,15 @@ struct PopIO {
     // scalar offset and the per-lane offset selects the rest, so a
     // wavefront with both kinds of lanes issues one store, not two.
     // Needs n + delta >= 0.
+    template <int AUX = 0>
     __device__ __forceinline__ void st_push(bool stream, int a, int b, int delta, uint32_t n,
                                             real v) const {
         const int lo = a < b ? a : b;
         if constexpr (BUF) {
             const uint32_t ds = (uint32_t)((int)((a - lo) * N) + delta);
             const uint32_t db = (uint32_t)(b - lo) * N;
-            buf_st<real>(v, rout, (n + (stream ? ds : db)) * (uint32_t)sizeof(real),
-                         (uint32_t)lo * N * (uint32_t)sizeof(real));
+            buf_st<real, AUX>(v, rout, (n + (stream ? ds : db)) * (uint32_t)sizeof(real),
+                              (uint32_t)lo * N * (uint32_t)sizeof(real));
         } else {
             fout[stream ? (int64_t)a * N + n + delta : (int64_t)b * N + n] = v;
         }

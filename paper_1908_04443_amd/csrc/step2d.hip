@@ -27,6 +27,7 @@
 #define LBM_PREC 0
 #endif
 #include <array>
+#include <type_traits>
 #include <utility>
 
 #include "tile2d.hpp"
@@ -58,6 +59,9 @@ __device__ __forceinline__ void d2q9_tile(const Coef<real>& C, const Fields<real
     int d_cnt = 0;
     // the tile and its 1-node ring lie inside the lattice without wrapping
     const bool interior = x0 >= 1 && y0 >= 1 && x0 + TX + 1 <= nx && y0 + TY + 1 <= ny;
+    // rows of every direction start on 128-byte boundaries
+    const bool lines = ((reinterpret_cast<uintptr_t>(Fd.fout) | ((uintptr_t)nx * sizeof(real)) |
+                         ((uintptr_t)x0 * sizeof(real))) & 127) == 0;
 
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
@@ -106,12 +110,26 @@ __device__ __forceinline__ void d2q9_tile(const Coef<real>& C, const Fields<real
         // push streaming with halfway bounce-back
         if (interior) {
             // no neighbour wraps: the target is n + ex + ey nx
+            // With rows on 128-byte boundaries, the directions with ex = 0
+            // fill whole cache lines of this tile (the rest population never
+            // leaves its node; the y neighbours of a row segment lie in one
+            // line segment), so those stores take the non-temporal policy.
+            // Shifts in x split lines with the neighbouring tile: normal.
+            auto push = [&](auto whole) {
+                constexpr bool NT_OK = decltype(whole)::value;
 #pragma unroll
-            for (int a = 0; a < 9; ++a) {
-                const int q = p + L::ex[a] + L::ey[a] * LX;
-                io.st_push(S.cls[q] == CLS_FLUID, a, L::opp[a], L::ex[a] + L::ey[a] * nx, n,
-                           fs[a]);
-            }
+                for (int a = 0; a < 9; ++a) {
+                    const int q = p + L::ex[a] + L::ey[a] * LX;
+                    if (NT_OK && L::ex[a] == 0)
+                        io.template st_push<ST_NT>(S.cls[q] == CLS_FLUID, a, L::opp[a],
+                                                   L::ey[a] * nx, n, fs[a]);
+                    else
+                        io.st_push(S.cls[q] == CLS_FLUID, a, L::opp[a], L::ex[a] + L::ey[a] * nx,
+                                   n, fs[a]);
+                }
+            };
+            if (lines) push(std::true_type{});
+            else push(std::false_type{});
         } else {
 #pragma unroll
             for (int a = 0; a < 9; ++a) {
