@@ -41,11 +41,22 @@ SMALL = dict(nx=24, ny=20, geometry=("disk", (12, 7), 4), init=("droplet", (12, 
              noise=1e-4, seed=11, sigma=0.105, precision=8)
 
 
+# one relaxation rate per moment group (Eq. 2), all different, in the row
+# order rho, e, eps, jx, qx, jy, qy, pxx, pxy
+TAU_DISTINCT = [1.0, 0.9, 1.2, 0.95, 1.1, 0.95, 1.1, 0.7, 0.7]
+
+
+@pytest.mark.parametrize("rates", ["equal", "distinct"])
 @pytest.mark.parametrize("scheme", ["ivd", "vd", "sfi"])
-def test_one_step_dot_product(oracle_mod, gpu_lib, scheme):
+def test_one_step_dot_product(oracle_mod, gpu_lib, scheme, rates):
+    """With distinct rates per moment group a transposed rate in the
+    collision's transpose would show; with equal rates it cancels."""
     import torch
     O = oracle_mod
-    s = Setup(O, dict(SMALL, scheme=scheme, rho_w=0.2, G_w=0.05))
+    case = dict(SMALL, scheme=scheme, rho_w=0.2, G_w=0.05)
+    if rates == "distinct":
+        case["tau"] = TAU_DISTINCT
+    s = Setup(O, case)
     rng = np.random.default_rng(3)
     phi = 1.0 + 0.2 * rng.random(len(s.walls))
     drho = 0.01 * rng.random(len(s.walls))
