@@ -236,7 +236,8 @@ int lbm_get_variant(lbm_ctx* ctx, int32_t* variant);
 /* Autotuner: times `steps` steps of every variant on the current problem
  * (HIP events on the context stream, after 2 warm-up steps each) and keeps
  * the fastest.  save_dev: device buffer of Q*N reals used to save and
- * restore the state, so that tuning leaves the fields unchanged; with NULL
+ * restore the state, so that tuning leaves the fields unchanged (scratch:
+ * it holds the context's internal form, pull form for D3Q19); with NULL
  * the state advances by nvariants*(steps+2) steps.  ms_per_variant (host,
  * nullable, lbm_variant_count entries) receives the mean step time of each.
  * If the environment variable LBM_AUTOTUNE_CACHE names a file, a cached
