@@ -119,7 +119,7 @@ def run_c2(L, W, steps, warmup):
     N = 256 ** 3
     nf = int((solid == 0).sum())
     s.close()
-    return dict(N=N, n_fluid=nf, n_wall=nw, wall=wall, ms_events=ms)
+    return dict(N=N, n_fluid=nf, n_wall=nw, wall=wall, ms_events=ms, params=p)
 
 
 def run_c3(L, W, steps, warmup, graph_steps=50):
@@ -257,6 +257,24 @@ def cpu_baseline(data, lbm_params, steps):
                 sample_1thread=f"{s1} steps on one thread ({dt1:.1f} s)")
 
 
+def cpu_oracle_c2(W, lbm_params, steps=4):
+    """The CPU oracle (FP64) on the 256^3 D3Q19 sphere workload, `steps` steps
+    from its initial state (a bounded sample: a step is a few seconds)."""
+    import oracle as O
+    op = O.make_params(lattice=19, nx=256, ny=256, nz=256, tau=1.0, T=lbm_params.eos_T,
+                       sigma=lbm_params.sigma, rho_g=lbm_params.rho_g, rho_l=lbm_params.rho_l)
+    data = W.c2_sphere(op.rho_g, op.rho_l)
+    solid = data["solid"]
+    walls = O.wall_nodes(op, solid)
+    f0 = O.init_eq(op, solid, data["rho"])
+    t0 = time.perf_counter()
+    O.run(op, solid, f0, steps, data["phi"].ravel()[walls], data["drho"].ravel()[walls])
+    dt = time.perf_counter() - t0
+    return dict(value=round(256 ** 3 * steps / dt / 1e6, 3), unit="MLUPS",
+                cores=O.get_threads(), kind="oracle",
+                sample=f"D3Q19 256^3 sphere workload, {steps} FP64 oracle step(s) ({dt:.1f} s)")
+
+
 def copy_calibration(nbytes, reps):
     """A plain device-to-device copy of known size, the reference point that
     converts the HBM counters of the profiler into bytes."""
@@ -355,6 +373,7 @@ def main():
     if "c2" in want:
         log(f"C2: D3Q19 256^3 FP32 sphere, {args.c2_steps} steps")
         c2 = run_c2(L, W, args.c2_steps, 20)
+        c2_params = c2.pop("params")
         k2 = c2["ms_events"] / 1e3 / args.c2_steps
         b2 = 2 * 19 * 4 * c2["n_fluid"]
         out["secondary"]["d3q19_256cubed_fp32"] = {
@@ -378,6 +397,9 @@ def main():
     if not args.no_cpu_baseline:
         log(f"CPU oracle: {args.cpu_steps} steps of the 2048^2 workload")
         out["cpu_baseline"] = cpu_baseline(c1["data"], c1["params"], args.cpu_steps)
+        if "c2" in want:
+            log("CPU oracle: 4 steps of the 256^3 D3Q19 workload")
+            out["secondary"]["d3q19_256cubed_fp32"]["cpu_oracle"] = cpu_oracle_c2(W, c2_params)
     print(json.dumps(out), flush=True)
 
 
