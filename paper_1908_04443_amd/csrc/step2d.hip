@@ -97,7 +97,13 @@ __device__ __forceinline__ void d2q9_tile(const Coef<real>& C, const Fields<real
                 Out.u[(size_t)N + n] = uy;
             }
             const real um = sqrt(ux * ux + uy * uy);
-            d_sum += (double)rho;
+            // mass: the node's populations summed in FP64 (in FP32 the
+            // density's own rounding repeats at every node of a uniform
+            // region and would bias the total)
+            double rs = (double)f[k][0];
+#pragma unroll
+            for (int a = 1; a < 9; ++a) rs += (double)f[k][a];
+            d_sum += rs;
             d_umax = um > d_umax ? um : d_umax;
             d_rmin = rho < d_rmin ? rho : d_rmin;
             d_rmax = rho > d_rmax ? rho : d_rmax;

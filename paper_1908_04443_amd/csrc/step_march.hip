@@ -362,7 +362,13 @@ __global__ __launch_bounds__(TX* TY, OCC) void k_step_march(Coef<real> C, Fields
                     }
                     if (Out.rho) Out.rho[n] = rho;
                     const real um = sqrt(uu);
-                    d_sum += (double)rho;
+                    // mass: the node's populations summed in FP64 (in FP32
+                    // the density's own rounding repeats at every node of a
+                    // uniform region and would bias the total)
+                    double rs = (double)fl[0];
+#pragma unroll
+                    for (int a = 1; a < Q; ++a) rs += (double)fl[a];
+                    d_sum += rs;
                     d_umax = um > d_umax ? um : d_umax;
                     d_rmin = rho < d_rmin ? rho : d_rmin;
                     d_rmax = rho > d_rmax ? rho : d_rmax;
