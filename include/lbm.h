@@ -95,7 +95,8 @@ typedef struct {
 
 /* Diagnostics of the current state (reductions over the fluid nodes). */
 typedef struct {
-    double mass;    /* sum of rho over fluid nodes (accumulated in double) */
+    double mass;    /* sum over fluid nodes of their populations (Eq. 4), each
+                       population added in double */
     double max_u;   /* max |u| over fluid nodes (spurious currents) */
     double rho_min; /* min rho over fluid nodes */
     double rho_max; /* max rho over fluid nodes */
