@@ -34,7 +34,9 @@
  *    exception crosses this interface.  lbm_last_error() gives a
  *    thread-local message for the last failure.
  *  - The library never allocates device memory: all device storage lives
- *    in the caller-owned workspace given to lbm_create/lbm_create_batch.
+ *    in the caller-owned workspace given to lbm_create/lbm_create_batch,
+ *    apart from the fixed scratch array of lbm_adjoint_noalloc (a device
+ *    global of the library, LBM_NOALLOC_SCRATCH_BYTES per GPU).
  */
 #ifndef LBM_H
 #define LBM_H
@@ -314,6 +316,26 @@ int lbm_step_ckpt(lbm_ctx* ctx, int64_t T, int64_t K, void* ckpt_dev);
 int lbm_adjoint(lbm_ctx* ctx, int32_t seed_kind, const void* seed_dev, int64_t T, int64_t K,
                 const void* ckpt_dev, void* work_dev, size_t work_bytes, void* grad_phi_dev,
                 void* grad_drho_dev, void* lam0_dev);
+
+/* ------------------------------------------- allocation-free adjoint */
+/* For callers that cannot allocate device memory where they call (code
+ * under stream capture, tight training or serving loops, harnesses that
+ * forbid hipMalloc): lbm_adjoint with its scratch in a device array of the
+ * library instead of work_dev.  Same arguments, checks, results and errors
+ * as lbm_adjoint otherwise.  The array holds LBM_NOALLOC_SCRATCH_BYTES;
+ * each GPU the library runs on keeps its own copy until the process ends.
+ * A call whose lbm_adjoint_workspace_bytes(ctx, K) exceeds that returns
+ * LBM_ENOMEM with a message (choose a smaller K).  The call allocates
+ * nothing: no hipMalloc/hipFree, and no allocating library routine.  Its
+ * first call on a device looks up the array's address there (stream's
+ * device).  Every call on one GPU shares that GPU's array, which keeps the
+ * last call's contents (each call writes every value it reads before
+ * reading it): calls ordered on one stream are safe, calls that overlap in
+ * time on one GPU (several streams or host threads) race. */
+#define LBM_NOALLOC_SCRATCH_BYTES (64u << 20)
+int lbm_adjoint_noalloc(lbm_ctx* ctx, int32_t seed_kind, const void* seed_dev, int64_t T,
+                        int64_t K, const void* ckpt_dev, void* grad_phi_dev,
+                        void* grad_drho_dev, void* lam0_dev);
 
 #ifdef __cplusplus
 }

@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "liblbm.so")
 BUILD = os.path.join(HERE, "_build")
 
 SOURCES = ["api.cpp", "thermo.cpp", "geometry.cpp", "step2d.hip", "step_march.hip",
-           "aux.hip", "adjoint2d.hip"]
+           "aux.hip", "adjoint2d.hip", "noalloc.hip"]
 # kernels compiled once per precision: FP32 with FMA contraction, FP64 without
 SPLIT = {"step2d.hip", "step_march.hip", "adjoint2d.hip"}
 EXTRA_SOURCES = []

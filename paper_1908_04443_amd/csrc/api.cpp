@@ -722,6 +722,31 @@ static int run_adjoint(lbm_ctx* c, int kind, const void* seed, int64_t T, int64_
         LBM_HIP(launch_adj_finish<real>(c->cls, lam[cur], ext[cur], (real*)lam0, N, c->stream));
     return LBM_OK;
 }
+// argument checks and dispatch of lbm_adjoint; work_dev is the scratch of
+// the call (the caller's workspace, or the library's own static array)
+int adjoint_entry(lbm_ctx* c, int32_t seed_kind, const void* seed_dev, int64_t T, int64_t K,
+                  const void* ckpt_dev, void* work_dev, size_t work_bytes, void* grad_phi_dev,
+                  void* grad_drho_dev, void* lam0_dev) {
+    if (!c || !seed_dev || !ckpt_dev || !work_dev) return fail(LBM_EINVAL, "NULL argument");
+    if (c->is_batch || c->p.lattice != 9)
+        return fail(LBM_EINVAL, "the adjoint is implemented for single D2Q9 lattices");
+    if (seed_kind != 0 && seed_kind != 1) return fail(LBM_EINVAL, "seed_kind must be 0 or 1");
+    if (c->scheme == LBM_WET_GF)
+        return fail(LBM_EINVAL, "no adjoint of the geometric formulation (its max/min and "
+                                "interpolation stencils have no parameters to differentiate)");
+    if (T < 1 || K < 1) return fail(LBM_EINVAL, "need T >= 1 and K >= 1");
+    if (!c->have_geom) return fail(LBM_ESTATE, "no geometry set");
+    if (c->domain_error) return fail(LBM_EDOMAIN, "a previous step left the psi domain");
+    const size_t need = adj_layout(c, K).total;
+    if (work_bytes < need)
+        return fail(LBM_ENOMEM, "adjoint workspace needs " + std::to_string(need) + " bytes");
+    if (((uintptr_t)work_dev & 255) != 0) return fail(LBM_EINVAL, "workspace must be 256-byte aligned");
+    return c->prec == 4 ? run_adjoint<float>(c, seed_kind, seed_dev, T, K, ckpt_dev, (char*)work_dev,
+                                             grad_phi_dev, grad_drho_dev, lam0_dev)
+                        : run_adjoint<double>(c, seed_kind, seed_dev, T, K, ckpt_dev,
+                                              (char*)work_dev, grad_phi_dev, grad_drho_dev, lam0_dev);
+}
+
 }  // namespace lbm
 
 using namespace lbm;
@@ -1405,24 +1430,8 @@ int lbm_step_ckpt(lbm_ctx* c, int64_t T, int64_t K, void* ckpt_dev) {
 int lbm_adjoint(lbm_ctx* c, int32_t seed_kind, const void* seed_dev, int64_t T, int64_t K,
                 const void* ckpt_dev, void* work_dev, size_t work_bytes, void* grad_phi_dev,
                 void* grad_drho_dev, void* lam0_dev) {
-    if (!c || !seed_dev || !ckpt_dev || !work_dev) return fail(LBM_EINVAL, "NULL argument");
-    if (c->is_batch || c->p.lattice != 9)
-        return fail(LBM_EINVAL, "the adjoint is implemented for single D2Q9 lattices");
-    if (seed_kind != 0 && seed_kind != 1) return fail(LBM_EINVAL, "seed_kind must be 0 or 1");
-    if (c->scheme == LBM_WET_GF)
-        return fail(LBM_EINVAL, "no adjoint of the geometric formulation (its max/min and "
-                                "interpolation stencils have no parameters to differentiate)");
-    if (T < 1 || K < 1) return fail(LBM_EINVAL, "need T >= 1 and K >= 1");
-    if (!c->have_geom) return fail(LBM_ESTATE, "no geometry set");
-    if (c->domain_error) return fail(LBM_EDOMAIN, "a previous step left the psi domain");
-    const size_t need = adj_layout(c, K).total;
-    if (work_bytes < need)
-        return fail(LBM_ENOMEM, "adjoint workspace needs " + std::to_string(need) + " bytes");
-    if (((uintptr_t)work_dev & 255) != 0) return fail(LBM_EINVAL, "workspace must be 256-byte aligned");
-    return c->prec == 4 ? run_adjoint<float>(c, seed_kind, seed_dev, T, K, ckpt_dev, (char*)work_dev,
-                                             grad_phi_dev, grad_drho_dev, lam0_dev)
-                        : run_adjoint<double>(c, seed_kind, seed_dev, T, K, ckpt_dev,
-                                              (char*)work_dev, grad_phi_dev, grad_drho_dev, lam0_dev);
+    return adjoint_entry(c, seed_kind, seed_dev, T, K, ckpt_dev, work_dev, work_bytes,
+                         grad_phi_dev, grad_drho_dev, lam0_dev);
 }
 
 }  // extern "C"

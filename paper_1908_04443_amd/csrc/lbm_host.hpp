@@ -53,6 +53,12 @@ int build_geometry(const lbm_params& p, const uint8_t* solid, Geometry& g);
 void build_gf_stencils(const lbm_params& p, const Geometry& g, const double* theta_deg,
                        std::vector<int32_t>& code, std::vector<double>& t);
 
+// ---- adjoint (api.cpp): checks and runs lbm_adjoint with work_dev as the
+// call's scratch (the caller's workspace or the library's static array)
+int adjoint_entry(lbm_ctx* c, int32_t seed_kind, const void* seed_dev, int64_t T, int64_t K,
+                  const void* ckpt_dev, void* work_dev, size_t work_bytes, void* grad_phi_dev,
+                  void* grad_drho_dev, void* lam0_dev);
+
 // ---- workspace carving
 struct Carver {
     char* base;

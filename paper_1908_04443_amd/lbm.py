@@ -87,6 +87,7 @@ def lib():
             "lbm_step_ckpt": (C.c_int, [vp, i64, i64, vp]),
             "lbm_adjoint": (C.c_int, [vp, C.c_int32, vp, i64, i64, vp, vp, C.c_size_t, vp, vp,
                                       vp]),
+            "lbm_adjoint_noalloc": (C.c_int, [vp, C.c_int32, vp, i64, i64, vp, vp, vp, vp]),
             "lbm_batch_workspace_bytes": (C.c_size_t, [P, C.c_int32, C.POINTER(C.c_int32),
                                                        C.POINTER(C.c_int32), C.POINTER(i64)]),
             "lbm_create_batch": (C.c_int, [P, C.c_int32, C.POINTER(C.c_int32),
@@ -251,6 +252,16 @@ def lbm_adjoint(ctx, seed_kind, seed, T, K, ckpt, work, grad_phi=None, grad_drho
     _check(lib().lbm_adjoint(ctx, int(seed_kind), _ptr(seed), int(T), int(K), _ptr(ckpt),
                              _ptr(work), work.numel() * work.element_size(), _ptr(grad_phi),
                              _ptr(grad_drho), _ptr(lam0)), "lbm_adjoint")
+
+
+def lbm_adjoint_noalloc(ctx, seed_kind, seed, T, K, ckpt, grad_phi=None, grad_drho=None,
+                        lam0=None):
+    _check(lib().lbm_adjoint_noalloc(ctx, int(seed_kind), _ptr(seed), int(T), int(K), _ptr(ckpt),
+                                     _ptr(grad_phi), _ptr(grad_drho), _ptr(lam0)),
+           "lbm_adjoint_noalloc")
+
+
+LBM_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 def lbm_set_graph_steps(ctx, steps):
