@@ -161,6 +161,24 @@ int lbm_set_geometry(lbm_ctx* ctx, const uint8_t* solid_host);
  * order used by the per-wall-node arrays of lbm_set_wetting/lbm_adjoint. */
 int lbm_wall_nodes(lbm_ctx* ctx, int64_t* idx_host, int64_t* count);
 
+/* Host query (no device, no context): the interpolation stencils of the
+ * geometric formulation (Sec. III A, Eqs. 11, 13-15) that a D2Q9 context
+ * with this solid mask and these angles steps with.  For wall node w (the
+ * order of lbm_wall_nodes) and characteristic point k (0: n_s turned by
+ * +(90 deg - theta_a), 1: by -(90 deg - theta_a)): nodes_host[8w+4k+2i],
+ * nodes_host[8w+4k+2i+1] are the x, y offsets of stencil node i (0, 1)
+ * from the wall node and weights_host[4w+2k+i] its weight in the density
+ * of the point.  Only fluid nodes carry weight; the weights of a point sum
+ * to 1, or are both 0 when the point is void.  theta_deg_host: one angle in
+ * degrees per wall node, or NULL for theta0.  *count receives the number of
+ * wall nodes; with both output arrays NULL nothing else is written,
+ * otherwise both must hold cap >= count entries.  Errors: LBM_EINVAL
+ * (parameters, lattice not D2Q9, an angle outside (0, 180), cap too
+ * small). */
+int lbm_gf_stencils(const lbm_params* p, const uint8_t* solid_host, const double* theta_deg_host,
+                    double theta0, int64_t cap, int64_t* count, int32_t* nodes_host,
+                    double* weights_host);
+
 /* Contact-angle scheme.
  *  LBM_WET_IVD  improved virtual density (Eqs. 16-17): per wall node b,
  *               rho_w = clamp(phi_b * rho_ave - drho_b, rho_g, rho_l), with

@@ -68,6 +68,7 @@ def lib():
         L.orc_lattice.argtypes = [C.c_int32, C.POINTER(C.c_int32), dp, dp, dp, dp,
                                   C.POINTER(C.c_int32)]
         L.orc_source.argtypes = [P, dp, dp, dp, C.c_double, dp]
+        L.orc_gf_points.argtypes = [P, u8, dp, dp]
         L.orc_set_threads.argtypes = [C.c_int]
         L.orc_get_threads.restype = C.c_int
         _lib = L
@@ -262,6 +263,18 @@ def state_tangent_cs(p, solid, f0, df0, nsteps, phi=None, drho=None, h=1e-30):
                                       _dp(f0), _dp(df0), int(nsteps), float(h),
                                       _dp(fo), _dp(dfo)), "state_tangent_cs")
     return fo, dfo
+
+
+def gf_points(p, solid, theta_deg):
+    """Geometric formulation at every wall node (wall order): an array of
+    shape (n_wall, 3, 2) holding the unit solid normal n_s and the points
+    D_1, D_2, relative to the node (NaN where no normal can be formed)."""
+    solid = np.ascontiguousarray(solid, dtype=np.uint8).ravel()
+    nw = len(wall_nodes(p, solid))
+    theta = np.ascontiguousarray(np.broadcast_to(np.asarray(theta_deg, np.float64), (nw,)))
+    out = np.zeros((max(nw, 1), 3, 2))
+    _check(lib().orc_gf_points(C.byref(p), _u8(solid), _dp(theta), _dp(out)), "gf_points")
+    return out[:nw]
 
 
 def set_threads(n):

@@ -340,73 +340,132 @@ static void work_free(work_t* w) {
 
 /* ------------------------------------------------------------------------
  * Curved geometric formulation (Sec. III A), 2-D.  For a wall node P:
- *   n_s  from Eq. 13 with the 8th-order isotropic weights of Eq. 14 over the
- *        24 neighbours with |e|^2 = 1, 2, 4, 5, 8 (s = 1 on solid nodes);
- *   n_1, n_2  n_s rotated by +-(pi/2 - theta_a), Eq. 15;
- *   D_k  the first crossing of the ray P + t n_k with a mesh line (the
- *        vertical lines x_P +- 1 or the horizontal lines y_P +- 1, whichever
- *        the ray meets first); rho(D_k) interpolates linearly between the two
- *        lattice nodes of that line segment, using only fluid nodes (one
- *        fluid node: its density; none: D_k is void; a crossing that falls
- *        on a lattice node is that node alone);
- *   rho_P = max(rho_D1, rho_D2) for theta_a <= 90 deg, min otherwise, Eq. 11
- *        (one void point: the other; both void: the neighbour mean of Eq. 17).
+ *   n_s  the unit solid normal of Eq. 13, -sum_e omega(|e|^2) s(P+e) e over
+ *        the 5 x 5 block around P without P itself (|e|^2 = 1, 2, 4, 5, 8),
+ *        with the 8th-order isotropic weights of Eq. 14 and s = 1 on solid
+ *        nodes;
+ *   n_1, n_2  n_s turned by +(pi/2 - theta_a) and -(pi/2 - theta_a), the
+ *        two characteristic directions of Eq. 15;
+ *   D_k  the point where the ray P + t n_k (t > 0) first meets one of the
+ *        four mesh lines that bound the 3 x 3 block around P (x = x_P - 1,
+ *        x_P + 1, y = y_P - 1, y_P + 1): every line is intersected and the
+ *        smallest positive t is kept, so D_k = t n_k;
+ *   rho(D_k)  interpolated from the position of D_k: the bilinear weights
+ *        (1 - |D_x - i|)(1 - |D_y - j|) of the four lattice nodes around
+ *        D_k, which on a mesh line reduce to the linear interpolation
+ *        between the two nodes of that line.  Nodes whose weight is below
+ *        GF_SNAP are not part of the stencil (D_k on a lattice node is that
+ *        node alone, whatever the rounding of t n_k).  Only fluid nodes
+ *        count: their weights are renormalised; no fluid node leaves D_k
+ *        void;
+ *   rho_P = max(rho(D_1), rho(D_2)) for theta_a <= 90 deg, else the min,
+ *        Eq. 11; one void point gives the other; two void points, or no
+ *        normal, give the w-weighted mean of the fluid neighbours (Eq. 17).
  * The paper leaves the location of D_1, D_2 to its Ref. [26]; this is the
- * reading taken here. */
+ * reading taken here.  A ray that meets two lines at one t passes through
+ * the corner node they share, so no choice between lines is ever made. */
+#define GF_SNAP 1e-12
+
 static int64_t node_at(const orc_params* p, int64_t n, int dx, int dy) {
     int32_t e[3] = {dx, dy, 0};
     return nbr(p, n, e);
 }
 
-static real gf_point(const orc_params* p, const uint8_t* solid, const real* rho,
-                     int64_t b, double vx, double vy, int* ok) {
-    double tx = fabs(vx) > 1e-12 ? 1.0 / fabs(vx) : 1e300;
-    double ty = fabs(vy) > 1e-12 ? 1.0 / fabs(vy) : 1e300;
-    int64_t na, nb;
-    double t;
-    if (tx <= ty) {
-        /* vertical mesh line x_P + sign(vx); crossing at y_P + tx vy */
-        int sx = vx > 0 ? 1 : -1;
-        double yc = tx * vy;
-        int y0 = (int)floor(yc);
-        t = yc - y0;
-        na = node_at(p, b, sx, y0);
-        nb = node_at(p, b, sx, y0 + 1);
-    } else {
-        int sy = vy > 0 ? 1 : -1;
-        double xc = ty * vx;
-        int x0 = (int)floor(xc);
-        t = xc - x0;
-        na = node_at(p, b, x0, sy);
-        nb = node_at(p, b, x0 + 1, sy);
+/* Eq. 14: weight of an offset of squared length e2 in the normal of Eq. 13 */
+static double gf_weight(int e2) {
+    switch (e2) {
+    case 1: return 4.0 / 21.0;
+    case 2: return 4.0 / 45.0;
+    case 4: return 1.0 / 60.0;
+    case 5: return 2.0 / 315.0;
+    case 8: return 1.0 / 5040.0;
+    default: return 0.0;
     }
-    int fa = !solid[na], fb = !solid[nb];
-    if (t == 0.0) fb = 0;  /* the crossing is the lattice node a itself */
-    *ok = fa || fb;
-    if (fa && fb) return (1.0 - t) * rho[na] + t * rho[nb];
-    if (fa) return rho[na];
-    if (fb) return rho[nb];
-    return 0.0;
+}
+
+/* Unit solid normal at wall node b (pointing out of the solid); 0 if the
+ * weighted sum vanishes. */
+static int gf_normal(const orc_params* p, const uint8_t* solid, int64_t b, double* n) {
+    double gx = 0.0, gy = 0.0;
+    for (int dy = -2; dy <= 2; ++dy)
+        for (int dx = -2; dx <= 2; ++dx) {
+            double om = gf_weight(dx * dx + dy * dy);
+            if (om == 0.0 || !solid[node_at(p, b, dx, dy)]) continue;
+            gx += om * dx;
+            gy += om * dy;
+        }
+    double len = hypot(gx, gy);
+    if (len == 0.0) return 0;
+    n[0] = -gx / len;
+    n[1] = -gy / len;
+    return 1;
+}
+
+/* D = t v at the smallest t > 0 where P + t v meets x = +-1 or y = +-1 */
+static void gf_crossing(const double* v, double* D) {
+    double best = INFINITY;
+    for (int axis = 0; axis < 2; ++axis)
+        for (int side = -1; side <= 1; side += 2) {
+            if (v[axis] == 0.0) continue;
+            double t = side / v[axis];
+            if (t > 0.0 && t < best) best = t;
+        }
+    D[0] = best * v[0];
+    D[1] = best * v[1];
+}
+
+/* rho at the point D (relative to wall node b): fluid nodes of its
+ * interpolation stencil with renormalised weights; *ok = 0 if none. */
+static real gf_rho_at(const orc_params* p, const uint8_t* solid, const real* rho, int64_t b,
+                      const double* D, int* ok) {
+    int i0 = (int)floor(D[0]), j0 = (int)floor(D[1]);
+    real acc = 0.0;
+    double wsum = 0.0;
+    for (int j = j0; j <= j0 + 1; ++j)
+        for (int i = i0; i <= i0 + 1; ++i) {
+            double w = (1.0 - fabs(D[0] - i)) * (1.0 - fabs(D[1] - j));
+            if (w < GF_SNAP) continue;
+            int64_t m = node_at(p, b, i, j);
+            if (solid[m]) continue;
+            acc += w * rho[m];
+            wsum += w;
+        }
+    *ok = wsum > 0.0;
+    return *ok ? acc / wsum : 0.0;
+}
+
+/* The two characteristic directions of Eq. 15 */
+static void gf_directions(const double* n, double theta_deg, double* v1, double* v2) {
+    const double pi = 3.14159265358979323846;
+    double turn = 0.5 * pi - theta_deg * (pi / 180.0);
+    double c = cos(turn), s = sin(turn);
+    v1[0] = c * n[0] - s * n[1];
+    v1[1] = s * n[0] + c * n[1];
+    v2[0] = c * n[0] + s * n[1];
+    v2[1] = -s * n[0] + c * n[1];
 }
 
 static real gf_density(const orc_params* p, const lat_t* L, const uint8_t* solid,
                        const real* rho, int64_t b, double theta_deg) {
-    static const int off[24][2] = {
-        {1, 0}, {-1, 0}, {0, 1}, {0, -1}, {1, 1}, {-1, 1}, {-1, -1}, {1, -1},
-        {2, 0}, {-2, 0}, {0, 2}, {0, -2}, {2, 1}, {1, 2}, {-1, 2}, {-2, 1},
-        {-2, -1}, {-1, -2}, {1, -2}, {2, -1}, {2, 2}, {-2, 2}, {-2, -2}, {2, -2}};
-    double sx = 0.0, sy = 0.0;
-    for (int i = 0; i < 24; ++i) {
-        int e2 = off[i][0] * off[i][0] + off[i][1] * off[i][1];
-        double om = e2 == 1 ? 4.0 / 21.0 : e2 == 2 ? 4.0 / 45.0 : e2 == 4 ? 1.0 / 60.0
-                  : e2 == 5 ? 2.0 / 315.0 : 1.0 / 5040.0;
-        if (solid[node_at(p, b, off[i][0], off[i][1])]) {
-            sx += om * off[i][0];
-            sy += om * off[i][1];
+    double n[2], v[2][2], D[2];
+    int have = gf_normal(p, solid, b, n);
+    real r[2] = {0.0, 0.0};
+    int ok[2] = {0, 0};
+    if (have) {
+        gf_directions(n, theta_deg, v[0], v[1]);
+        for (int k = 0; k < 2; ++k) {
+            gf_crossing(v[k], D);
+            r[k] = gf_rho_at(p, solid, rho, b, D, &ok[k]);
         }
     }
-    double norm = sqrt(sx * sx + sy * sy);
-    /* Eq. 17, the standard case, when no direction can be formed */
+    if (ok[0] && ok[1]) {
+        int take_min = theta_deg > 90.0;
+        int first = take_min ? RE(r[0]) <= RE(r[1]) : RE(r[0]) >= RE(r[1]);
+        return first ? r[0] : r[1];
+    }
+    if (ok[0]) return r[0];
+    if (ok[1]) return r[1];
+    /* Eq. 17, the standard case */
     real num = 0.0;
     double den = 0.0;
     for (int a = 1; a < L->Q; ++a) {
@@ -416,23 +475,36 @@ static real gf_density(const orc_params* p, const lat_t* L, const uint8_t* solid
             den += L->w[a];
         }
     }
-    real rave = num / den;
-    if (norm == 0.0) return rave;
-    double nx = -sx / norm, ny = -sy / norm;
-    const double pi = 3.14159265358979323846;
-    double th = theta_deg * (pi / 180.0), tp = 0.5 * pi - th;
-    double c = cos(tp), s = sin(tp);
-    double n1x = nx * c - ny * s, n1y = nx * s + ny * c;
-    double n2x = nx * c + ny * s, n2y = -nx * s + ny * c;
-    int ok1, ok2;
-    real r1 = gf_point(p, solid, rho, b, n1x, n1y, &ok1);
-    real r2 = gf_point(p, solid, rho, b, n2x, n2y, &ok2);
-    if (!ok1 && !ok2) return rave;
-    if (!ok1) return r2;
-    if (!ok2) return r1;
-    if (theta_deg <= 90.0) return RE(r1) >= RE(r2) ? r1 : r2;
-    return RE(r1) <= RE(r2) ? r1 : r2;
+    return num / den;
 }
+
+#ifndef ORC_COMPLEX
+/* For the pins: n_s, D_1 and D_2 of every wall node, relative to the node
+ * (6 doubles per wall node, in wall-list order; NaN without a normal). */
+int orc_gf_points(const orc_params* p, const uint8_t* solid, const double* theta_deg,
+                  double* out) {
+    if (check_params(p) != ORC_OK || p->lattice != 9) return ORC_EINVAL;
+    int64_t nw = orc_wall_nodes(p, solid, NULL);
+    int64_t* walls = malloc((size_t)(nw > 0 ? nw : 1) * sizeof(int64_t));
+    if (!walls) return ORC_EINVAL;
+    orc_wall_nodes(p, solid, walls);
+    for (int64_t k = 0; k < nw; ++k) {
+        double n[2], v[2][2];
+        double* o = out + 6 * k;
+        if (gf_normal(p, solid, walls[k], n)) {
+            gf_directions(n, theta_deg[k], v[0], v[1]);
+            o[0] = n[0];
+            o[1] = n[1];
+            gf_crossing(v[0], o + 2);
+            gf_crossing(v[1], o + 4);
+        } else {
+            for (int i = 0; i < 6; ++i) o[i] = NAN;
+        }
+    }
+    free(walls);
+    return ORC_OK;
+}
+#endif
 
 /* Phases 1-5 of the step: density, psi, wall virtual density, force and
  * velocity at time t from the post-streaming populations f. */

@@ -61,6 +61,13 @@ int orc_coexistence(const orc_params* p, double* rho_g, double* rho_l);
  * order. */
 int64_t orc_wall_nodes(const orc_params* p, const uint8_t* solid, int64_t* idx);
 
+/* The construction of the geometric formulation (Sec. III A, Eqs. 13-15) at
+ * every wall node, for the pins: theta_deg one angle per wall node (wall
+ * order); out 6 doubles per wall node: the unit normal n_s and the points
+ * D_1, D_2, relative to the node (NaN where no normal can be formed). */
+int orc_gf_points(const orc_params* p, const uint8_t* solid, const double* theta_deg,
+                  double* out);
+
 /* ---- real-valued state ---- */
 int orc_init_eq(const orc_params* p, const uint8_t* solid, const double* rho0,
                 const double* u0 /* [D][N] or NULL */, double* f);

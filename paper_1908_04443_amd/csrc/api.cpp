@@ -880,6 +880,48 @@ int lbm_set_geometry(lbm_ctx* c, const uint8_t* solid_host) {
     return LBM_OK;
 }
 
+int lbm_gf_stencils(const lbm_params* p, const uint8_t* solid_host, const double* theta_deg_host,
+                    double theta0, int64_t cap, int64_t* count, int32_t* nodes_host,
+                    double* weights_host) {
+    const int rc = validate(p);
+    if (rc != LBM_OK) return rc;
+    if (!solid_host || !count) return fail(LBM_EINVAL, "NULL argument");
+    if (p->lattice != 9) return fail(LBM_EINVAL, "the geometric formulation is two-dimensional");
+    Geometry g;
+    build_geometry(*p, solid_host, g);
+    const int64_t nw = (int64_t)g.walls.size();
+    *count = nw;
+    if (!nodes_host && !weights_host) return LBM_OK;
+    if (!nodes_host || !weights_host) return fail(LBM_EINVAL, "need both output arrays");
+    if (cap < nw) return fail(LBM_EINVAL, "output arrays hold fewer entries than wall nodes");
+    std::vector<double> th(nw, theta0);
+    if (theta_deg_host)
+        for (int64_t i = 0; i < nw; ++i) th[i] = theta_deg_host[i];
+    for (int64_t i = 0; i < nw; ++i)
+        if (!(th[i] > 0.0 && th[i] < 180.0))
+            return fail(LBM_EINVAL, "geometric formulation: angles must lie in (0, 180) degrees");
+    std::vector<int32_t> code;
+    std::vector<double> t;
+    build_gf_stencils(*p, g, th.data(), code, t);
+    // decode: the weight of each fluid stencil node, as the step applies it
+    for (int64_t w = 0; w < nw; ++w)
+        for (int k = 0; k < 2; ++k) {
+            const int f = (code[w] >> (10 * k)) & 0x3FF;
+            const int ia = f & 15, ib = (f >> 4) & 15;
+            const bool fa = (f >> 8) & 1, fb = (f >> 9) & 1;
+            const double tt = t[2 * w + k];
+            int32_t* nd = nodes_host + 8 * w + 4 * k;
+            double* wt = weights_host + 4 * w + 2 * k;
+            nd[0] = ia % 3 - 1;
+            nd[1] = ia / 3 - 1;
+            nd[2] = ib % 3 - 1;
+            nd[3] = ib / 3 - 1;
+            wt[0] = fa ? (fb ? 1.0 - tt : 1.0) : 0.0;
+            wt[1] = fb ? (fa ? tt : 1.0) : 0.0;
+        }
+    return LBM_OK;
+}
+
 int lbm_wall_nodes(lbm_ctx* c, int64_t* idx_host, int64_t* count) {
     if (!c || !count) return fail(LBM_EINVAL, "NULL argument");
     if (c->is_batch) return fail(LBM_EINVAL, "multi-case context: use the _case call");

@@ -123,10 +123,13 @@ void build_gf_stencils(const lbm_params& p, const Geometry& g, const double* the
                 tt = xc - x0;
                 ax = x0; ay = sgn; bx = x0 + 1; by = sgn;
             }
-            // a crossing exactly on a lattice node (tt == 0) is that node
-            // alone; only then can b fall outside the 3x3 block
-            const bool fa = ax >= -1 && ax <= 1 && ay >= -1 && ay <= 1 && !solid_at(x + ax, y + ay);
-            const bool fb = tt != 0.0 && bx >= -1 && bx <= 1 && by >= -1 && by <= 1 &&
+            // a crossing within 1e-12 of a lattice node is that node alone
+            // (whatever the rounding of the crossing); b can fall outside the
+            // 3x3 block only when the crossing is node a
+            const bool at_a = tt < 1e-12, at_b = tt > 1.0 - 1e-12;
+            const bool fa = !at_b && ax >= -1 && ax <= 1 && ay >= -1 && ay <= 1 &&
+                            !solid_at(x + ax, y + ay);
+            const bool fb = !at_a && bx >= -1 && bx <= 1 && by >= -1 && by <= 1 &&
                             !solid_at(x + bx, y + by);
             const int ia = (fa ? (ax + 1) + 3 * (ay + 1) : 0), ib = (fb ? (bx + 1) + 3 * (by + 1) : 0);
             c |= (ia | (ib << 4) | ((int)fa << 8) | ((int)fb << 9)) << (10 * k);

@@ -70,6 +70,8 @@ def lib():
             "lbm_destroy": (C.c_int, [vp]),
             "lbm_set_geometry": (C.c_int, [vp, C.POINTER(C.c_uint8)]),
             "lbm_wall_nodes": (C.c_int, [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+            "lbm_gf_stencils": (C.c_int, [P, C.POINTER(C.c_uint8), dp, C.c_double, i64,
+                                          C.POINTER(C.c_int64), C.POINTER(C.c_int32), dp]),
             "lbm_set_wetting": (C.c_int, [vp, C.c_int32, C.c_double, vp, vp, C.c_double,
                                           C.c_double]),
             "lbm_set_fields": (C.c_int, [vp, vp, vp]),
@@ -177,6 +179,29 @@ def lbm_wall_nodes(ctx):
     _check(lib().lbm_wall_nodes(ctx, idx.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(n)),
            "lbm_wall_nodes")
     return idx[:n.value]
+
+
+def lbm_gf_stencils(params, solid, theta_deg=None, theta0=90.0):
+    """Host query: the geometric-formulation stencils of every wall node.
+    Returns (nodes, weights): int32 (n_wall, 2, 2, 2) offsets [wall, point,
+    node, xy] and float64 (n_wall, 2, 2) weights [wall, point, node]."""
+    solid = np.ascontiguousarray(solid, dtype=np.uint8).ravel()
+    u8 = solid.ctypes.data_as(C.POINTER(C.c_uint8))
+    n = C.c_int64()
+    _check(lib().lbm_gf_stencils(C.byref(params), u8, None, float(theta0), 0, C.byref(n), None,
+                                 None), "lbm_gf_stencils")
+    nw = n.value
+    th = None
+    if theta_deg is not None:
+        th = np.ascontiguousarray(np.broadcast_to(np.asarray(theta_deg, np.float64), (nw,)))
+    nodes = np.zeros((max(nw, 1), 2, 2, 2), dtype=np.int32)
+    wts = np.zeros((max(nw, 1), 2, 2))
+    _check(lib().lbm_gf_stencils(C.byref(params), u8,
+                                 None if th is None else th.ctypes.data_as(C.POINTER(C.c_double)),
+                                 float(theta0), max(nw, 1), C.byref(n),
+                                 nodes.ctypes.data_as(C.POINTER(C.c_int32)),
+                                 wts.ctypes.data_as(C.POINTER(C.c_double))), "lbm_gf_stencils")
+    return nodes[:nw], wts[:nw]
 
 
 def lbm_set_wetting(ctx, scheme, scalar=0.0, phi=None, drho=None, phi0=1.0, drho0=0.0):
