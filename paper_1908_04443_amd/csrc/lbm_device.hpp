@@ -243,6 +243,38 @@ struct PopIO {
     }
 };
 
+// Four consecutive nodes n .. n+3 of FP32 direction a in one 16-byte
+// buffer access (n a multiple of 4: the rows of a lattice whose width is a
+// multiple of 4 start on 16-byte boundaries).  The partial store writes
+// three consecutive nodes (12 bytes, 4-byte aligned).
+// (The whole vector is bit-cast to floats before its elements are taken:
+// a bit-cast of one element of an integer vector reads element 0.)
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x3 __attribute__((ext_vector_type(3)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void ld_quad(const PopIO<float, true>& io, int a, uint32_t n,
+                                        float& v0, float& v1, float& v2, float& v3) {
+    const f32x4 r = __builtin_bit_cast(
+        f32x4, __builtin_amdgcn_raw_buffer_load_b128(io.rin, (int)(n * 4u), (int)(a * io.N * 4u), 0));
+    v0 = r.x;
+    v1 = r.y;
+    v2 = r.z;
+    v3 = r.w;
+}
+template <int AUX = 0>
+__device__ __forceinline__ void st_quad(const PopIO<float, true>& io, int a, uint32_t n, float v0,
+                                        float v1, float v2, float v3) {
+    const u32x4 w = {__builtin_bit_cast(unsigned, v0), __builtin_bit_cast(unsigned, v1),
+                     __builtin_bit_cast(unsigned, v2), __builtin_bit_cast(unsigned, v3)};
+    __builtin_amdgcn_raw_buffer_store_b128(w, io.rout, (int)(n * 4u), (int)(a * io.N * 4u), AUX);
+}
+__device__ __forceinline__ void st_triple(const PopIO<float, true>& io, int a, uint32_t n, float v0,
+                                          float v1, float v2) {
+    const u32x3 w = {__builtin_bit_cast(unsigned, v0), __builtin_bit_cast(unsigned, v1),
+                     __builtin_bit_cast(unsigned, v2)};
+    __builtin_amdgcn_raw_buffer_store_b96(w, io.rout, (int)(n * 4u), (int)(a * io.N * 4u), 0);
+}
+
 __device__ __forceinline__ int wrapi(int v, int n) {
     // any integer into [0, n); tiles may cover the lattice several times
     v %= n;

@@ -31,6 +31,7 @@
 #include <utility>
 
 #include "tile2d.hpp"
+#include "tile2d_vec.hpp"
 
 namespace lbm {
 
@@ -181,6 +182,17 @@ __global__ __launch_bounds__(NT, OCC) void k_step_d2q9(Coef<real> C, Fields<real
                                                 by * gxb + bx);
 }
 
+// The same step with 16-byte population accesses (tile2d_vec.hpp): FP32,
+// lattices whose width is a multiple of 4, arrays below 4 GiB.
+template <int TX, int TY, int NT, bool XCD, int OCC, bool GFW>
+__global__ __launch_bounds__(NT, OCC) void k_step_d2q9_vec(Coef<float> C, Fields<float> Fd) {
+    const int gxb = gridDim.x, gyb = gridDim.y, nblk = gxb * gyb;
+    int bid = blockIdx.x + gxb * blockIdx.y;
+    if (XCD) bid = remap_xcd(bid, nblk);
+    const int bx = bid % gxb, by = bid / gxb;
+    d2q9_tile_vec<TX, TY, NT, GFW>(C, Fd, C.nx, C.ny, bx * TX, by * TY, by * gxb + bx);
+}
+
 // Many independent lattices in one launch: workgroup -> (case, tile) through
 // a table; each case has its own size, node classes, wall list and wetting
 // parameters inside packed arenas.  The physical parameters are shared.
@@ -215,19 +227,22 @@ struct Shape2D {
     bool xcd;
     int ord;  // column-group width of the tile order (0: row-major)
     int occ;  // minimum waves per SIMD asked of the register allocator
+    bool vec = false;  // 16-byte accesses (FP32 step, width a multiple of 4)
 };
 
 template <typename real>
 struct Variants2D;
 template <>
 struct Variants2D<float> {
-    static constexpr int count = 12;
+    static constexpr int count = 16;
     static constexpr int preferred = 10;  // 128 x 16 tiles, 512 threads
     static constexpr Shape2D shape[count] = {
         {64, 16, 256, true, 0, 1},  {64, 16, 256, false, 0, 1}, {128, 8, 256, true, 0, 1},
         {64, 32, 256, true, 0, 1},  {256, 4, 256, true, 0, 1},  {128, 16, 256, true, 0, 1},
         {64, 16, 256, true, 8, 1},  {128, 8, 256, true, 4, 1},  {64, 16, 256, true, 0, 8},
-        {256, 8, 512, true, 0, 1},  {128, 16, 512, true, 0, 1}, {64, 32, 256, true, 8, 1}};
+        {256, 8, 512, true, 0, 1},  {128, 16, 512, true, 0, 1}, {64, 32, 256, true, 8, 1},
+        {128, 16, 512, true, 0, 1, true}, {64, 16, 256, true, 0, 1, true},
+        {256, 8, 512, true, 0, 1, true},  {128, 32, 512, true, 0, 1, true}};
 };
 template <>
 struct Variants2D<double> {
@@ -256,6 +271,14 @@ static void launch_v(const Coef<real>& C, const Fields<real>& F, const FieldOut<
                      hipStream_t s) {
     constexpr Shape2D sh = Variants2D<real>::shape[V];
     dim3 grid((C.nx + sh.TX - 1) / sh.TX, (C.ny + sh.TY - 1) / sh.TY);
+    if constexpr (sh.vec && std::is_same<real, float>::value && MODE == MODE_STEP && BUF) {
+        if (C.nx % 4 == 0) {
+            hipLaunchKernelGGL((k_step_d2q9_vec<sh.TX, sh.TY, sh.NT, sh.xcd, sh.occ, GFW>), grid,
+                               dim3(sh.NT), 0, s, C, F);
+            return;
+        }
+    }
+    // otherwise the scalar tile of the same shape (the wall lists match)
     hipLaunchKernelGGL(
         (k_step_d2q9<real, sh.TX, sh.TY, sh.NT, MODE, sh.xcd, BUF, sh.ord, sh.occ, GFW>), grid,
         dim3(sh.NT), 0, s, C, F, O);

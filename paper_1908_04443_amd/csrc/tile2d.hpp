@@ -94,6 +94,132 @@ __device__ __forceinline__ real gf_density(const uint8_t* cls, const real* rho, 
     return r[0] >= r[1] ? r[0] : r[1];
 }
 
+// Per-thread entry of the tile's wall list (see wall_list_head)
+template <typename real>
+struct WallEntry {
+    bool on = false, gf = false;
+    uint32_t e0 = 0;
+    int pos = -1;
+    int32_t code = 0;
+    real phi = real(0), drho = real(0);
+};
+
+// The first wave loads the first 64 entries of the tile's wall list (if the
+// context has lists for the scheme); the count goes to LDS.
+template <typename real, bool GFW>
+__device__ __forceinline__ void wall_list_head(const Coef<real>& C, const Fields<real>& Fd,
+                                               int list_tile, int tid, int& lds_count,
+                                               WallEntry<real>& we) {
+    we.gf = GFW && C.scheme == WET_GF;
+    we.on = (C.scheme == WET_IVD || we.gf) && Fd.tw_pack != nullptr;
+    if (!we.on) return;
+    we.e0 = (uint32_t)list_tile * (uint32_t)Fd.tw_stride;
+    if (tid < 64) {
+        const int w = Fd.tw_pack[we.e0 + tid];
+        we.phi = Fd.tw_phi[we.e0 + tid];
+        we.drho = Fd.tw_drho[we.e0 + tid];
+        if (we.gf) we.code = Fd.tw_code[we.e0 + tid];
+        if (tid < (w >> 16)) we.pos = w & 0xFFFF;
+        if (tid == 0) lds_count = w >> 16;
+    }
+}
+
+// Second phase of the prologue, after the barrier that follows the loads
+// (LDS holds the classes and densities of the tile plus a 2-node halo):
+// wall virtual densities (Eqs. 16-17 and the limiter, the constant virtual
+// density, the geometric formulation of Eq. 11, or none for Eq. 8) and psi
+// (Eq. 6) on the tile plus a 1-node halo; ends with a barrier.
+template <typename real, int TX, int TY, int NT, bool GFW>
+__device__ __forceinline__ void d2q9_psi_phase(const Coef<real>& C, const Fields<real>& Fd,
+                                               TileLDS<real, TX, TY>& S, WallEntry<real>& we,
+                                               bool& bad) {
+    using L = D2Q9;
+    constexpr int LX = TX + 4;
+    const int tid = threadIdx.x;
+    // wall-list entries beyond the first 64
+    if (we.on && tid >= 64 && tid < S.wl_count) {
+        we.pos = Fd.tw_pack[we.e0 + tid] & 0xFFFF;
+        we.phi = Fd.tw_phi[we.e0 + tid];
+        we.drho = Fd.tw_drho[we.e0 + tid];
+        if (we.gf) we.code = Fd.tw_code[we.e0 + tid];
+    }
+
+    // psi on tile + 1 halo; wall nodes first get their virtual density
+    // (with a wall list, the listed walls are done below by their entries)
+    for (int i = tid; i < (TX + 2) * (TY + 2); i += NT) {
+        const int lx = 1 + i % (TX + 2), ly = 1 + i / (TX + 2);
+        const int p = ly * LX + lx;
+        const uint8_t c = S.cls[p];
+        real ps = real(0);
+        if (c == CLS_WALL && we.on) continue;
+        if (c == CLS_FLUID) {
+            ps = psi_of(C, S.rho[p], bad);
+        } else if (c == CLS_WALL) {
+            if (C.scheme == WET_IVD) {
+                // Eq. 17: w-weighted mean over the fluid neighbours
+                real num = real(0), den = real(0);
+                bool first = true;
+#pragma unroll
+                for (int a = 1; a < 9; ++a) {
+                    const int q = p + L::ex[a] + L::ey[a] * LX;
+                    if (S.cls[q] == CLS_FLUID) {
+                        const real w = real(L::w12[a]) * real(1.0 / 12.0);
+                        num = first ? w * S.rho[q] : num + w * S.rho[q];
+                        den = first ? w : den + w;
+                        first = false;
+                    }
+                }
+                const real rave = fdiv(num, den);
+                const int kw = Fd.widx[S.row[ly] + S.col[lx]];
+                // Eq. 16 (phi scales, drho shifts) and the limiter
+                real rw = Fd.phi[kw] * rave - Fd.drho[kw];
+                rw = rw > C.rho_l ? C.rho_l : rw;
+                rw = rw < C.rho_g ? C.rho_g : rw;
+                S.rho[p] = rw;
+                ps = psi_of(C, rw, bad);
+            } else if (we.gf) {
+                const int kw = Fd.widx[S.row[ly] + S.col[lx]];
+                const real rw = gf_density<real, LX>(S.cls, S.rho, p, Fd.gfcode[kw], Fd.phi[kw],
+                                                     Fd.drho[kw]);
+                S.rho[p] = rw;
+                ps = psi_of(C, rw, bad);
+            } else if (C.scheme == WET_VD) {
+                S.rho[p] = C.rho_w;
+                ps = C.psi_w;
+            } else {
+                S.rho[p] = real(0);
+            }
+        }
+        S.psi[p] = ps;
+    }
+    if (we.pos >= 0 && we.gf) {
+        const real rw = gf_density<real, LX>(S.cls, S.rho, we.pos, we.code, we.phi, we.drho);
+        S.rho[we.pos] = rw;
+        S.psi[we.pos] = psi_of(C, rw, bad);
+    } else if (we.pos >= 0) {
+        // Eq. 17 over the fluid neighbours, Eq. 16 and the limiter
+        const int p = we.pos;
+        real num = real(0), den = real(0);
+        bool first = true;
+#pragma unroll
+        for (int a = 1; a < 9; ++a) {
+            const int q = p + L::ex[a] + L::ey[a] * LX;
+            if (S.cls[q] == CLS_FLUID) {
+                const real w = real(L::w12[a]) * real(1.0 / 12.0);
+                num = first ? w * S.rho[q] : num + w * S.rho[q];
+                den = first ? w : den + w;
+                first = false;
+            }
+        }
+        real rw = we.phi * fdiv(num, den) - we.drho;
+        rw = rw > C.rho_l ? C.rho_l : rw;
+        rw = rw < C.rho_g ? C.rho_g : rw;
+        S.rho[p] = rw;
+        S.psi[p] = psi_of(C, rw, bad);
+    }
+    __syncthreads();
+}
+
 // GFW: the geometric formulation is compiled in (a separate instantiation,
 // so that the other schemes keep its registers out of their kernels)
 template <typename real, int TX, int TY, int NT, bool BUF, bool GFW = false>
@@ -129,23 +255,8 @@ __device__ __forceinline__ void d2q9_prologue(const Coef<real>& C, const Fields<
     // Per-tile wall list (improved virtual density, geometric formulation):
     // the first wave loads the first 64 entries with the other loads of
     // this phase; entries beyond 64 (rare) follow after the barrier.
-    const bool gf = GFW && C.scheme == WET_GF;
-    const bool wl_on = (C.scheme == WET_IVD || gf) && Fd.tw_pack != nullptr;
-    uint32_t wl_e0 = 0;
-    int wl_pos = -1;
-    int32_t wl_code = 0;
-    real wl_phi = real(0), wl_drho = real(0);
-    if (wl_on) {
-        wl_e0 = (uint32_t)list_tile * (uint32_t)Fd.tw_stride;
-        if (tid < 64) {
-            const int w = Fd.tw_pack[wl_e0 + tid];
-            wl_phi = Fd.tw_phi[wl_e0 + tid];
-            wl_drho = Fd.tw_drho[wl_e0 + tid];
-            if (gf) wl_code = Fd.tw_code[wl_e0 + tid];
-            if (tid < (w >> 16)) wl_pos = w & 0xFFFF;
-            if (tid == 0) S.wl_count = w >> 16;
-        }
-    }
+    WallEntry<real> we;
+    wall_list_head<real, GFW>(C, Fd, list_tile, tid, S.wl_count, we);
 
     // owned tile nodes: populations into registers, density into LDS
     uint8_t oc[RPT];
@@ -200,88 +311,7 @@ __device__ __forceinline__ void d2q9_prologue(const Coef<real>& C, const Fields<
     }
     __syncthreads();
 
-    // wall-list entries beyond the first 64
-    if (wl_on && tid >= 64 && tid < S.wl_count) {
-        wl_pos = Fd.tw_pack[wl_e0 + tid] & 0xFFFF;
-        wl_phi = Fd.tw_phi[wl_e0 + tid];
-        wl_drho = Fd.tw_drho[wl_e0 + tid];
-        if (gf) wl_code = Fd.tw_code[wl_e0 + tid];
-    }
-
-    // psi on tile + 1 halo; wall nodes first get their virtual density
-    // (with a wall list, the listed walls are done below by their entries)
-    for (int i = tid; i < (TX + 2) * (TY + 2); i += NT) {
-        const int lx = 1 + i % (TX + 2), ly = 1 + i / (TX + 2);
-        const int p = ly * LX + lx;
-        const uint8_t c = S.cls[p];
-        real ps = real(0);
-        if (c == CLS_WALL && wl_on) continue;
-        if (c == CLS_FLUID) {
-            ps = psi_of(C, S.rho[p], bad);
-        } else if (c == CLS_WALL) {
-            if (C.scheme == WET_IVD) {
-                // Eq. 17: w-weighted mean over the fluid neighbours
-                real num = real(0), den = real(0);
-                bool first = true;
-#pragma unroll
-                for (int a = 1; a < 9; ++a) {
-                    const int q = p + L::ex[a] + L::ey[a] * LX;
-                    if (S.cls[q] == CLS_FLUID) {
-                        const real w = real(L::w12[a]) * real(1.0 / 12.0);
-                        num = first ? w * S.rho[q] : num + w * S.rho[q];
-                        den = first ? w : den + w;
-                        first = false;
-                    }
-                }
-                const real rave = fdiv(num, den);
-                const int kw = Fd.widx[S.row[ly] + S.col[lx]];
-                // Eq. 16 (phi scales, drho shifts) and the limiter
-                real rw = Fd.phi[kw] * rave - Fd.drho[kw];
-                rw = rw > C.rho_l ? C.rho_l : rw;
-                rw = rw < C.rho_g ? C.rho_g : rw;
-                S.rho[p] = rw;
-                ps = psi_of(C, rw, bad);
-            } else if (gf) {
-                const int kw = Fd.widx[S.row[ly] + S.col[lx]];
-                const real rw = gf_density<real, LX>(S.cls, S.rho, p, Fd.gfcode[kw], Fd.phi[kw],
-                                                     Fd.drho[kw]);
-                S.rho[p] = rw;
-                ps = psi_of(C, rw, bad);
-            } else if (C.scheme == WET_VD) {
-                S.rho[p] = C.rho_w;
-                ps = C.psi_w;
-            } else {
-                S.rho[p] = real(0);
-            }
-        }
-        S.psi[p] = ps;
-    }
-    if (wl_pos >= 0 && gf) {
-        const real rw = gf_density<real, LX>(S.cls, S.rho, wl_pos, wl_code, wl_phi, wl_drho);
-        S.rho[wl_pos] = rw;
-        S.psi[wl_pos] = psi_of(C, rw, bad);
-    } else if (wl_pos >= 0) {
-        // Eq. 17 over the fluid neighbours, Eq. 16 and the limiter
-        const int p = wl_pos;
-        real num = real(0), den = real(0);
-        bool first = true;
-#pragma unroll
-        for (int a = 1; a < 9; ++a) {
-            const int q = p + L::ex[a] + L::ey[a] * LX;
-            if (S.cls[q] == CLS_FLUID) {
-                const real w = real(L::w12[a]) * real(1.0 / 12.0);
-                num = first ? w * S.rho[q] : num + w * S.rho[q];
-                den = first ? w : den + w;
-                first = false;
-            }
-        }
-        real rw = wl_phi * fdiv(num, den) - wl_drho;
-        rw = rw > C.rho_l ? C.rho_l : rw;
-        rw = rw < C.rho_g ? C.rho_g : rw;
-        S.rho[p] = rw;
-        S.psi[p] = psi_of(C, rw, bad);
-    }
-    __syncthreads();
+    d2q9_psi_phase<real, TX, TY, NT, GFW>(C, Fd, S, we, bad);
 }
 
 // Eq. 5 cohesive force and Eq. 8 adhesion at LDS position p; returns the
