@@ -136,8 +136,12 @@ int lbm_eos_eval(const lbm_params* p, double rho, double* p_eos, double* psi);
  * the parameters are invalid. */
 size_t lbm_workspace_bytes(const lbm_params* p, int64_t n_wall_max);
 
-/* Create a context.  stream: a hipStream_t (NULL = default stream) on which
- * every launch and copy of this context is ordered.  workspace: device
+/* Create a context for one lattice of the problem Sec. IV A states (size,
+ * periodic box, equation of state and temperature of Eq. 6 / Eq. 18,
+ * relaxation times of Eq. 2, the constant sigma of Eq. 7, interaction
+ * strength G of Eq. 5, limiter bounds of Sec. III B).  stream: a
+ * hipStream_t (NULL = default stream) on which every launch and copy of
+ * this context is ordered.  workspace: device
  * memory of ws_bytes >= lbm_workspace_bytes(p, n_wall_max), owned by the
  * caller and kept alive (and not touched) until lbm_destroy.  Errors:
  * LBM_EINVAL (parameters), LBM_ENOMEM (workspace too small),
@@ -223,18 +227,26 @@ int lbm_set_state(lbm_ctx* ctx, const void* f_dev);
 
 /* --------------------------------------------------------------- steps */
 /* Advance nsteps >= 0 time steps, asynchronously on the context stream.
+ * One step is Eq. 4 (density), Eq. 6 (psi), the wall virtual density of
+ * the scheme (Eqs. 16-17, Eq. 11, or none for Eq. 8), Eq. 5 (+ Eq. 8 and
+ * the body force), Eq. 2 with the forcing of Eq. 7, and Eq. 3 streaming
+ * with halfway bounce-back at the staircase wall (Fig. 3).
  * Errors: LBM_ESTATE (geometry or fields unset), LBM_EDOMAIN if a previous
  * diagnostics call found the domain flag set (sticky until new fields). */
 int lbm_step(lbm_ctx* ctx, int64_t nsteps);
 
-/* Macroscopic fields of the current state, written stream-ordered to
+/* Macroscopic fields of the current state (Eq. 4: rho = sum_a f_a and
+ * u = (sum_a e_a f_a + F/2) / rho with the total force F of the step),
+ * written stream-ordered to
  * caller device arrays (each may be NULL): rho_dev N reals (fluid: density;
  * wall nodes: their virtual density, 0 under SFI; other solid: 0), u_dev
  * D*N reals ([D][N], 0 on solid), f_dev Q*N reals (the post-stream
  * populations, 0 on solid). */
 int lbm_get_fields(lbm_ctx* ctx, void* rho_dev, void* u_dev, void* f_dev);
 
-/* Reductions over the current state; synchronises the context stream.
+/* Reductions over the current state (the quantities Figs. 10-11 compare:
+ * maximum spurious current, extreme fluid densities; plus the mass of
+ * Eq. 4 summed over the fluid); synchronises the context stream.
  * Returns LBM_EDOMAIN (and sets the sticky error) if the device domain flag
  * is set. */
 int lbm_get_diagnostics(lbm_ctx* ctx, lbm_diag* host_out);

@@ -417,6 +417,9 @@ class Solver:
 
     def set_geometry(self, solid):
         lbm_set_geometry(self.ctx, solid)
+        # fluid-node mask on the device (the seed of the adjoint uses only
+        # fluid entries; LBMRollout returns rho on fluid nodes only)
+        self.fluid = torch.as_tensor(np.asarray(solid).ravel() == 0, device=self.device)
 
     def wall_nodes(self):
         return lbm_wall_nodes(self.ctx)
@@ -509,21 +512,30 @@ class LBMRollout(torch.autograd.Function):
     """rho(T) of a D2Q9 lattice as a differentiable function of the
     per-wall-node parameters (phi, drho) of the improved virtual-density
     scheme.  Forward: T steps from the initial density rho0 with
-    checkpoints every K steps; backward: the hand-written discrete adjoint
-    (checkpointed recomputation), seeded with dL/drho(T) on fluid nodes."""
+    checkpoints every K steps; returns rho(T) on the fluid nodes and 0 on
+    every solid node (the wall nodes' virtual densities are left out, so
+    any loss of the output is a function of the fluid state only).
+    Backward: the hand-written discrete adjoint (checkpointed
+    recomputation), seeded with dL/drho(T) on the fluid nodes, under the
+    parameters of this forward (set again before the adjoint runs, in case
+    the solver was used in between)."""
 
     @staticmethod
     def forward(ctx, phi, drho, solver, rho0, T, K):
-        solver.set_wetting(LBM_WET_IVD, 0.0, phi.detach().contiguous(), drho.detach().contiguous())
+        phi_d, drho_d = phi.detach().contiguous().clone(), drho.detach().contiguous().clone()
+        solver.set_wetting(LBM_WET_IVD, 0.0, phi_d, drho_d)
         solver.set_fields(rho0)
         ckpt = solver.ckpt_buffer(T, K)
         solver.step_ckpt(T, K, ckpt)
         rho_T = solver.get_fields(rho=True, u=False)["rho"]
+        rho_T = torch.where(solver.fluid, rho_T, torch.zeros_like(rho_T))
         ctx.solver, ctx.T, ctx.K, ctx.ckpt = solver, T, K, ckpt
+        ctx.phi, ctx.drho = phi_d, drho_d
         return rho_T
 
     @staticmethod
     def backward(ctx, grad_rho):
+        ctx.solver.set_wetting(LBM_WET_IVD, 0.0, ctx.phi, ctx.drho)
         gp, gd = ctx.solver.adjoint(grad_rho.contiguous(), ctx.T, ctx.K, ctx.ckpt)
         return gp, gd, None, None, None, None
 

@@ -169,12 +169,18 @@ def test_c4_adjoint_vs_central_differences(oracle_mod, gpu_lib):
     seed = 2.0 * np.where(fluid, rho_T - target, 0.0)
     gp, gd = (g.cpu().numpy() for g in sol.adjoint(seed, T, K, ckpt))
     L0, _ = _run_loss(gpu_lib, sol, phi0, drho0, d["rho"].ravel(), T, target, fluid)
+    h = 1e-6
+    # resolution of FP64 central differences: the loss carries a relative
+    # rounding of about 1e-14 (a sum over 6e4 nodes of a deterministic FP64
+    # run), so a difference quotient is good to 1e-14 L0 / h; an entry can be
+    # checked to 1e-5 relative only if |dL/dp| is 1e5 times that
+    floor = 1e5 * 1e-14 * abs(L0) / h
     rng = np.random.default_rng(4)
-    live = np.flatnonzero((np.abs(gp) + np.abs(gd)) > 0)  # walls not held by the limiter
+    live = np.flatnonzero(np.minimum(np.abs(gp), np.abs(gd)) > 2.0 * floor)
+    print(f"L0 = {L0:.6e}; FD floor {floor:.3e}; {len(live)} of {len(gp)} wall nodes above it")
     assert len(live) >= 16
     picks = rng.choice(live, 16, replace=False)
-    checked = 0
-    h = 1e-6
+    checked = skipped = 0
     for k in picks:
         for which, g in ((0, gp), (1, gd)):
             pp, pm = phi0.copy(), phi0.copy()
@@ -189,14 +195,20 @@ def test_c4_adjoint_vs_central_differences(oracle_mod, gpu_lib):
             lm, _ = _run_loss(gpu_lib, sol, pm, dm, d["rho"].ravel(), T, target, fluid)
             fd = (lp - lm) / (2 * h)
             fwd, bwd = (lp - L0) / h, (L0 - lm) / h
-            scale = max(abs(fd), 1e-2 * np.abs(g).max())
-            if abs(fwd - bwd) > 2e-5 * scale:
+            if abs(fwd - bwd) > 1e-3 * abs(fd):
+                # a limiter switch inside +-h: the loss has a kink there, and
+                # the one-sided slopes differ by a share of the slope itself
+                # (smooth curvature makes them differ by h L'' only, a few
+                # 1e-5 of the slope for the drho entries here)
                 print(f"wall {k}: one-sided slopes differ ({fwd:.6e} vs {bwd:.6e}), skipped")
+                skipped += 1
                 continue
             checked += 1
-            print(f"wall {k} {'phi' if which == 0 else 'drho'}: adj {g[k]:.10e} fd {fd:.10e}")
-            assert abs(g[k] - fd) <= 1e-5 * scale
-    assert checked >= 20
+            print(f"wall {k} {'phi' if which == 0 else 'drho'}: adj {g[k]:.10e} fd {fd:.10e} "
+                  f"rel {abs(g[k] - fd) / abs(fd):.2e}")
+            assert abs(g[k] - fd) <= 1e-5 * abs(fd)
+    print(f"{checked} entries checked, {skipped} skipped at a limiter switch")
+    assert skipped <= 4 and checked >= 28
 
 
 def test_fp32_adjoint_tracks_fp64(oracle_mod, gpu_lib):
@@ -248,6 +260,43 @@ def test_autograd_function_matches_direct_adjoint(oracle_mod, gpu_lib):
                                   np.full(nw, 1.05), np.full(nw, 0.001))[1] for k in range(nw)])
     g = phi.grad.cpu().numpy()
     assert np.abs(g - cs).max() <= 1e-9 * np.abs(cs).max()
+
+
+def test_autograd_unmasked_loss_and_interleaved_forward(oracle_mod, gpu_lib):
+    """L = sum over every node of (rho_T - target)^2, walls included: the
+    rollout returns 0 on solid nodes, so L is the fluid loss plus a
+    constant and its gradient must equal the oracle's complex-step one.  A
+    second forward with other parameters runs on the same solver between
+    the forward and the backward of the first; the backward must still use
+    the first forward's parameters."""
+    import torch
+    O = oracle_mod
+    s = Setup(O, dict(SMALL, scheme="ivd"))
+    sol = _solver(gpu_lib, s)
+    nw = len(s.walls)
+    rng = np.random.default_rng(12)
+    phi0 = 1.0 + 0.15 * rng.random(nw)
+    drho0 = 0.002 * rng.random(nw)
+    phi = torch.tensor(phi0, dtype=torch.float64, device="cuda", requires_grad=True)
+    drho = torch.tensor(drho0, dtype=torch.float64, device="cuda", requires_grad=True)
+    rho0 = torch.as_tensor(s.rho0.ravel(), device="cuda")
+    target = torch.full_like(rho0, 0.1)  # nonzero on solid nodes too
+    T, K = 20, 6
+    rho_T = gpu_lib.LBMRollout.apply(phi, drho, sol, rho0, T, K)
+    loss = ((rho_T - target) ** 2).sum()
+    with torch.no_grad():  # another forward in between, other parameters
+        gpu_lib.LBMRollout.apply(phi * 1.1, drho + 0.01, sol, rho0, T, K)
+    loss.backward()
+    tgt = target.cpu().numpy()
+    cs_p = np.array([O.loss_grad_cs(s.op, s.solid, s.f0, T, tgt, 0, k, phi0, drho0)[1]
+                     for k in range(nw)])
+    cs_d = np.array([O.loss_grad_cs(s.op, s.solid, s.f0, T, tgt, 1, k, phi0, drho0)[1]
+                     for k in range(nw)])
+    ep = np.abs(phi.grad.cpu().numpy() - cs_p).max() / np.abs(cs_p).max()
+    ed = np.abs(drho.grad.cpu().numpy() - cs_d).max() / np.abs(cs_d).max()
+    print(f"unmasked loss: phi grad rel err {ep:.2e}, drho grad rel err {ed:.2e}")
+    assert ep <= 1e-9 and ed <= 1e-9
+    assert torch.all(rho_T.detach()[torch.as_tensor(s.solid.ravel() != 0, device="cuda")] == 0)
 
 
 def test_inverse_design_recovers_wall_parameters(oracle_mod, gpu_lib):

@@ -91,6 +91,25 @@ def test_batch_every_tile_shape_vs_oracle(oracle_mod, gpu_lib, variant):
         assert err <= 1e-12 and uerr <= 1e-12, (i, err, uerr)
 
 
+@pytest.mark.parametrize("variant", range(16))  # the FP32 tile shapes
+def test_batch_fp32_tile_shapes_vs_oracle(oracle_mod, gpu_lib, variant):
+    """Every FP32 tile shape of the multi-case launch (the 16-byte variants'
+    shapes run the scalar multi-case tile) against the FP64 oracle, FP32
+    normwise bars: 1e-4 on rho, 1e-3 on u."""
+    from paper_1908_04443_amd import lbm
+    if variant >= lbm.lbm_variant_count(9, 4) - 3:  # the y-sweep variants are single-lattice
+        pytest.skip("no such tile shape")
+    setups = [Setup(oracle_mod, c) for c in _case_dicts(4)]
+    b = _batch(gpu_lib, setups, 80, variant=variant)
+    for i, s in enumerate(setups):
+        f = oracle_mod.run(s.op, s.solid, s.f0, 80, s.phi, s.drho)
+        rho_o, u_o, _ = oracle_mod.fields(s.op, s.solid, f, s.phi, s.drho)
+        out = b.get_fields(i)
+        err = np.abs(out["rho"].double().cpu().numpy() - rho_o).max() / np.abs(rho_o).max()
+        uerr = np.abs(out["u"].double().cpu().numpy() - u_o).max() / np.abs(u_o).max()
+        assert err <= 1e-4 and uerr <= 1e-3, (i, err, uerr)
+
+
 def test_batch_diagnostics_are_case_totals(oracle_mod, gpu_lib):
     setups = [Setup(oracle_mod, c) for c in _case_dicts(8)]
     b = _batch(gpu_lib, setups, 30)
