@@ -67,15 +67,24 @@ def setup_solver(L, W, params, data, n_wall_max):
     return s, len(walls)
 
 
-def time_steps(s, warmup, steps):
+def time_steps(s, warmup, steps, segments=5):
+    """Warm up, then time exactly `steps` steps as `segments` consecutive
+    runs, each bracketed by HIP events on the solver's stream.  Returns the
+    wall-clock time of all of them (synchronised before and after) and the
+    median event time per step over the segments."""
+    import numpy as np
     import torch
     s.step(warmup)
     torch.cuda.synchronize()
+    sizes = [steps // segments + (1 if i < steps % segments else 0) for i in range(segments)]
+    per_step = []
     t0 = time.perf_counter()
-    ms_events = s.step_timed(steps)
+    for n in sizes:
+        if n:
+            per_step.append(s.step_timed(n) / n)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    return wall, ms_events
+    return wall, float(np.median(per_step)), [round(x, 5) for x in per_step]
 
 
 def run_c1(L, W, steps, warmup):
@@ -87,7 +96,7 @@ def run_c1(L, W, steps, warmup):
     s, nw = setup_solver(L, W, p, data, int(solid.sum()))
     rc, d0 = s.diagnostics()
     variant = s.variant
-    wall, ms = time_steps(s, warmup, steps)
+    wall, ms_step, seg = time_steps(s, warmup, steps)
     # diagnostics (field-mode pass over f, per-tile partials, fixed-order
     # final reduction, copy to the host and a stream synchronisation)
     s.diagnostics()
@@ -100,8 +109,8 @@ def run_c1(L, W, steps, warmup):
     N = 2048 * 2048
     nf = int((solid == 0).sum())
     s.close()
-    return dict(N=N, n_fluid=nf, n_wall=nw, wall=wall, ms_events=ms, variant=variant,
-                diag_ms=diag_ms,
+    return dict(N=N, n_fluid=nf, n_wall=nw, wall=wall, ms_step=ms_step, segments=seg,
+                variant=variant, diag_ms=diag_ms,
                 mass_drift=abs(d1["mass"] - d0["mass"]) / d0["mass"], max_u=d1["max_u"],
                 rho=(d1["rho_min"], d1["rho_max"]), data=data, params=p)
 
@@ -112,21 +121,23 @@ def run_c2(L, W, steps, warmup):
     data = W.c2_sphere(p.rho_g, p.rho_l)
     solid = data["solid"]
     s, nw = setup_solver(L, W, p, data, int(solid.sum()))
-    wall, ms = time_steps(s, warmup, steps)
+    wall, ms_step, seg = time_steps(s, warmup, steps)
     rc, d1 = s.diagnostics()
     if rc != 0:
         raise RuntimeError("C2 run left the psi domain")
     N = 256 ** 3
     nf = int((solid == 0).sum())
     s.close()
-    return dict(N=N, n_fluid=nf, n_wall=nw, wall=wall, ms_events=ms, params=p)
+    return dict(N=N, n_fluid=nf, n_wall=nw, wall=wall, ms_step=ms_step, segments=seg, params=p)
 
 
 def run_c3(L, W, steps, warmup, graph_steps=50):
     """96 D2Q9 FP32 cases of uneven size: one multi-case context (tile shape
     picked by the autotuner) replaying a graph of `graph_steps` steps,
-    against one context per case (its default tile shape) stepped in turn on
-    the same stream with plain launches."""
+    against one context per case stepped in turn on the same stream, both
+    with its default tile shape and plain launches and tuned (autotuned tile
+    shape, graph replay)."""
+    import numpy as np
     import torch
     p = L.make_params(lattice=9, precision=4, nx=1, ny=1, T_ratio=0.75,
                       sigma=W.SIGMA[("cs", 0.75, 9)], tau=1.0)
@@ -154,28 +165,51 @@ def run_c3(L, W, steps, warmup, graph_steps=50):
     rc, d = b.diagnostics()
     if rc != 0:
         raise RuntimeError("batched run left the psi domain")
+    # the multi-case kernel alone: HIP events around `steps` graph-replayed
+    # steps, median of 5 runs
+    kern_ms = float(np.median([b.step_timed(steps) / steps for _ in range(5)]))
+    nf_total = sum(int((c["solid"] == 0).sum()) for c in cases)
     b.close()
 
-    sols = []
-    for c in cases:
-        q = L.make_params(lattice=9, precision=4, nx=c["n"], ny=c["n"], T=p.eos_T, sigma=p.sigma,
-                          tau=1.0, rho_g=p.rho_g, rho_l=p.rho_l)
-        s1, _ = setup_solver(L, W, q, c, int(c["solid"].sum()))
-        sols.append(s1)
-    for s1 in sols:
-        s1.step(warmup)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s1 in sols:
-        s1.step(steps)
-    torch.cuda.synchronize()
-    t_single = time.perf_counter() - t0
-    for s1 in sols:
-        s1.close()
+    def singles(tune, graphs):
+        sols = []
+        for c in cases:
+            q = L.make_params(lattice=9, precision=4, nx=c["n"], ny=c["n"], T=p.eos_T,
+                              sigma=p.sigma, tau=1.0, rho_g=p.rho_g, rho_l=p.rho_l)
+            s1, _ = setup_solver(L, W, q, c, int(c["solid"].sum()))
+            if tune:
+                s1.autotune(steps=10)
+            if graphs:
+                s1.set_graph_steps(graph_steps)
+            sols.append(s1)
+        for s1 in sols:
+            s1.step(warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s1 in sols:
+            s1.step(steps)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        for s1 in sols:
+            s1.close()
+        return t
+
+    # one context per case, launched in turn on one stream: as configured by
+    # default (the tile preferred for large lattices, plain launches), and
+    # tuned (each case's fastest tile shape, graph replay)
+    t_single = singles(False, False)
+    t_tuned = singles(True, True)
+    b_alg = 2 * 9 * 4 * nf_total
     return dict(total_nodes=total, cases=len(cases), steps=steps,
                 batched_mlups=total * steps / t_batch / 1e6,
                 single_mlups=total * steps / t_single / 1e6,
-                ratio=t_single / t_batch, graph_steps=graph_steps, batch_tile_variant=tuned)
+                single_tuned_mlups=total * steps / t_tuned / 1e6,
+                ratio=t_single / t_batch, ratio_vs_tuned_single=t_tuned / t_batch,
+                graph_steps=graph_steps, batch_tile_variant=tuned,
+                batch_kernel=dict(kernel="k_step_d2q9_batch", kernel_ms=round(kern_ms, 5),
+                                  bytes_per_launch_alg=b_alg,
+                                  achieved_GBs=round(b_alg / (kern_ms * 1e-3) / 1e9, 1),
+                                  frac=round(b_alg / (kern_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)))
 
 
 def run_c4(L, W, T=1000, K=50):
@@ -192,6 +226,10 @@ def run_c4(L, W, T=1000, K=50):
     s, nw = setup_solver(L, W, p, d, int(d["solid"].sum()))
     s.step(50)
     # medians of 5 runs: the 256^2 step is short enough for launch jitter to show
+    fwd_ms_default = float(np.median([s.step_timed(T) / T for _ in range(5)]))
+    # the forward at its fastest tile shape on this lattice (the adjoint's
+    # own tiles fill the chip; the default forward tile leaves most CUs idle)
+    fwd_variant = s.autotune(steps=50)
     fwd_ms = float(np.median([s.step_timed(T) / T for _ in range(5)]))
     s.set_fields(d["rho"].ravel())
     ckpt = s.ckpt_buffer(T, K)
@@ -214,11 +252,14 @@ def run_c4(L, W, T=1000, K=50):
     adj_ms = float(np.median(runs))
     nseg = (T + K - 1) // K
     recompute = T - nseg
-    adj_step_ms = (adj_ms - recompute * fwd_ms) / T
+    adj_step_ms = (adj_ms - recompute * fwd_ms) / T  # the recompute runs the tuned forward
     s.close()
     return dict(T=T, K=K, wall_nodes=nw, forward_step_ms=round(fwd_ms, 5),
+                forward_tile_variant=fwd_variant,
+                forward_step_ms_default_tile=round(fwd_ms_default, 5),
                 adjoint_step_ms=round(adj_step_ms, 5),
                 adjoint_step_over_forward=round(adj_step_ms / fwd_ms, 3),
+                adjoint_step_over_forward_default_tile=round(adj_step_ms / fwd_ms_default, 3),
                 backward_total_ms=round(adj_ms, 3), checkpointed_forward_ms=round(ckpt_ms, 3),
                 backward_over_forward=round(adj_ms / (fwd_ms * T), 3),
                 grad_finite=bool(torch.isfinite(gp).all() and torch.isfinite(gd).all()))
@@ -251,10 +292,22 @@ def cpu_baseline(data, lbm_params, steps):
     finally:
         O.set_threads(threads)
     return dict(value=N * steps / dt / 1e6, unit="MLUPS", cores=threads, kind="oracle",
+                cpu_model=cpu_model(),
                 sample=f"D2Q9 2048x2048 porous workload, same initial state, {steps} FP64 "
                        f"oracle steps ({dt:.1f} s)",
                 value_1thread=N * s1 / dt1 / 1e6,
                 sample_1thread=f"{s1} steps on one thread ({dt1:.1f} s)")
+
+
+def cpu_model():
+    """The host CPU's model name (Linux /proc/cpuinfo)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_oracle_c2(W, lbm_params, steps=4):
@@ -327,7 +380,7 @@ def main():
     N, nf = c1["N"], c1["n_fluid"]
     ms_step = 1e3 * c1["wall"] / args.steps
     mlups = N * args.steps / c1["wall"] / 1e6
-    kern_s = c1["ms_events"] / 1e3 / args.steps
+    kern_s = c1["ms_step"] / 1e3  # HIP-event time per step, median of 5 segments
     b_alg = 2 * 9 * 4 * nf  # one read + one write of every fluid population
     achieved = b_alg / kern_s / 1e9
     traffic = measured_traffic("k_step_d2q9", "c1")
@@ -356,7 +409,8 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
                      "kernel": "k_step_d2q9", "bytes_per_launch_alg": b_alg,
-                     "kernel_ms": round(kern_s * 1e3, 5)},
+                     "kernel_ms": round(kern_s * 1e3, 5),
+                     "kernel_ms_segments": c1["segments"]},
         "check": {"mass_rel_drift": c1["mass_drift"], "max_u": c1["max_u"],
                   "rho_min_max": c1["rho"]},
         # one read of every fluid population per diagnostics call
@@ -374,13 +428,14 @@ def main():
         log(f"C2: D3Q19 256^3 FP32 sphere, {args.c2_steps} steps")
         c2 = run_c2(L, W, args.c2_steps, 20)
         c2_params = c2.pop("params")
-        k2 = c2["ms_events"] / 1e3 / args.c2_steps
+        k2 = c2["ms_step"] / 1e3
         b2 = 2 * 19 * 4 * c2["n_fluid"]
         out["secondary"]["d3q19_256cubed_fp32"] = {
             "mlups": round(c2["N"] * args.c2_steps / c2["wall"] / 1e6, 2),
             "achieved_GBs": round(b2 / k2 / 1e9, 1),
             "frac": round(b2 / k2 / 1e9 / HBM_PEAK_GBS, 4),
-            "kernel_ms": round(k2 * 1e3, 5), "steps": args.c2_steps,
+            "kernel_ms": round(k2 * 1e3, 5), "kernel_ms_segments": c2["segments"],
+            "steps": args.c2_steps,
             "traffic": measured_traffic("d3q19_step", "c2")}
         log(f"C2: {out['secondary']['d3q19_256cubed_fp32']}")
     if "c3" in want:

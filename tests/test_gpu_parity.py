@@ -11,11 +11,13 @@ import numpy as np
 import pytest
 
 from cases import Setup, run_gpu
+from paper_1908_04443_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
+# the 128^2 cylinder workload with its 60 deg wetting parameters
 C0 = dict(nx=128, ny=128, geometry=("disk", (64, 64), 24), init=("droplet", (64, 108), 20),
-          scheme="ivd", phi=1.2, noise=1e-6, seed=0, precision=8)
+          scheme="ivd", phi=W.PHI_C0_60, drho=0.0, noise=1e-6, seed=0, precision=8)
 
 
 def _fluid(setup):
@@ -75,7 +77,11 @@ def test_c0_fp32_mass_conservation(oracle_mod, gpu_lib):
 def test_c0_equilibrium_angle_fp32_vs_oracle(oracle_mod, gpu_lib):
     """The 128^2 case run to equilibrium (20000 steps): the contact angle of
     the FP32 GPU run within 0.5 deg of the FP64 oracle's (both measured by
-    the same circle fit of the droplet's free interface)."""
+    the same circle fit of the droplet's free interface), and the oracle's
+    within 3 deg of the 60 deg the workload targets: on this staircase
+    cylinder the settled angle jumps from 63.6 to 57.3 deg between
+    phi = 1.2212 and 1.2326, so 60 deg itself is not reached and the
+    workload takes the closest settled angle below it."""
     from paper_1908_04443_amd import analysis as A
     O = oracle_mod
     s = Setup(O, dict(C0, precision=4))
@@ -90,6 +96,7 @@ def test_c0_equilibrium_angle_fp32_vs_oracle(oracle_mod, gpu_lib):
         angles.append(th)
     print(f"theta FP32 GPU {angles[0]:.3f}, FP64 oracle {angles[1]:.3f}", flush=True)
     assert abs(angles[0] - angles[1]) <= 0.5
+    assert abs(angles[1] - 60.0) <= 3.0
 
 
 @pytest.mark.parametrize("scheme", ["ivd", "vd", "sfi"])

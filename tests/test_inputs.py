@@ -114,3 +114,15 @@ def test_wall_counts_of_the_workload_geometries(oracle_mod):
     p = O.make_params(lattice=19, nx=256, ny=256, nz=256, T_ratio=0.8, sigma=0.1)
     assert len(O.wall_nodes(p, d2["solid"])) == 25088
     assert int(d2["solid"].sum()) == 267761
+
+
+def test_c0_phi_is_the_stored_cylinder_calibration():
+    """The 128^2 workload's wetting parameter is the value the committed
+    oracle calibration on that cylinder found (tests/golden/calibrate_c0.py)."""
+    import json
+    import os
+    cal = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c0_calibration.json")))
+    assert W.PHI_C0_60 == cal["phi"]
+    assert abs(cal["measured_deg"] - 60.0) <= 3.0
+    d = W.c0_cylinder(0.02, 0.3)
+    assert np.all(d["phi"] == W.PHI_C0_60) and np.all(d["drho"] == 0.0)
