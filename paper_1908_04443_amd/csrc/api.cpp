@@ -103,7 +103,10 @@ static Fields<real> make_fields(const lbm_ctx* c, int src) {
     F.phi = (const real*)c->phi;
     F.drho = (const real*)c->drho;
     F.flag = c->flag;
-    F.rho = (real*)c->rho;
+    F.rho = (real*)c->rho_buf[c->rho_idx];
+    F.rho_next = (real*)c->rho_buf[c->rho_idx ^ 1];
+    F.ring = (real*)c->ring;
+    F.rho_valid = c->rho_valid;
     F.gfcode = c->gfcode;
     return F;
 }
@@ -141,6 +144,12 @@ static size_t layout(const lbm_params& p, int64_t nwm, lbm_ctx* c) {
     double* part = cv.take<double>(5 * (size_t)nparts);
     double* dout = cv.take<double>(8);
     void* rho = cv.take<char>((size_t)N * s);  // density pass of the sweep kernels
+    // D3Q19: the density a PSUM step forms, and its per-block partial sums
+    void* rho2 = cv.take<char>(Q == 19 ? (size_t)N * s : 0);
+    const size_t ring_el = Q != 19 ? 0
+                           : (p.precision == 4 ? step3d_ring_elems<float>(p.nx, p.ny, p.nz)
+                                               : step3d_ring_elems<double>(p.nx, p.ny, p.nz));
+    void* ring = cv.take<char>(ring_el * s);
     // per-tile wall lists: up to 256 entries per tile of the tile variant
     // with the most tiles (D2Q9 only)
     int64_t twcap = 0;
@@ -159,7 +168,9 @@ static size_t layout(const lbm_params& p, int64_t nwm, lbm_ctx* c) {
     int32_t* twc = cv.take<int32_t>(twcap);
     int32_t* gfc = cv.take<int32_t>(nw);
     if (c) {
-        c->rho = rho;
+        c->rho_buf[0] = rho;
+        c->rho_buf[1] = Q == 19 ? rho2 : rho;
+        c->ring = ring;
         c->tw_code = twc;
         c->gfcode = gfc;
         c->tw_pack = twp;
@@ -190,6 +201,7 @@ static int launch_mode(lbm_ctx* c, int mode, real* rho, real* u, double* part) {
     hipError_t e = (c->p.lattice == 9) ? launch_step2d<real>(C, F, O, mode, 0, c->stream)
                                        : launch_step3d<real>(C, F, O, mode, 0, c->stream);
     if (e != hipSuccess) return fail(LBM_EDEVICE, std::string("step launch: ") + hipGetErrorString(e));
+    if (c->p.lattice == 19) c->rho_valid = true;  // the field pass used or formed it
     return LBM_OK;
 }
 
@@ -216,9 +228,12 @@ static int ensure_tiles(lbm_ctx* c) {
     return LBM_OK;
 }
 
-// one step from buffer `src` to `src ^ 1`, launched on stream s
+// one step from buffer `src` to `src ^ 1`, launched on stream s; D3Q19
+// steps read the density buffer ridx (already the density of src when
+// rvalid) and a PSUM step writes the next one into ridx ^ 1
 template <typename real>
-static hipError_t launch_one(lbm_ctx* c, const Coef<real>& C, int src, hipStream_t s) {
+static hipError_t launch_one(lbm_ctx* c, const Coef<real>& C, int src, hipStream_t s,
+                             int ridx = 0, bool rvalid = false) {
     if (c->is_batch) {
         BatchArgs<real> B;
         B.fin = (const real*)c->f[src];
@@ -240,6 +255,9 @@ static hipError_t launch_one(lbm_ctx* c, const Coef<real>& C, int src, hipStream
         return launch_step2d_batch<real>(C, B, c->ntiles, c->variant, s);
     }
     Fields<real> F = make_fields<real>(c, src);
+    F.rho = (real*)c->rho_buf[ridx];
+    F.rho_next = (real*)c->rho_buf[ridx ^ 1];
+    F.rho_valid = rvalid;
     if (c->tw_stride > 0 && c->tw_variant == c->variant) {
         F.tw_pack = c->tw_pack;
         F.tw_phi = (const real*)c->tw_phi;
@@ -266,12 +284,17 @@ template <typename real>
 static int capture_graph(lbm_ctx* c, const Coef<real>& C) {
     drop_graph(c);
     if (!c->cap_stream) LBM_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    // a PSUM variant's graph starts from a valid density (run_steps makes
+    // it so before every replay) and keeps it valid; other variants run the
+    // density pass in every captured step
+    const bool forms = c->Q == 19 && step3d_forms_density<real>(C, c->variant);
     LBM_HIP(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
-    int src = c->cur;
+    int src = c->cur, ridx = c->rho_idx;
     hipError_t e = hipSuccess;
     for (int64_t i = 0; i < c->graph_steps && e == hipSuccess; ++i) {
-        e = launch_one<real>(c, C, src, c->cap_stream);
+        e = launch_one<real>(c, C, src, c->cap_stream, ridx, forms);
         src ^= 1;
+        if (forms) ridx ^= 1;
     }
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
@@ -282,7 +305,7 @@ static int capture_graph(lbm_ctx* c, const Coef<real>& C) {
     }
     c->graph = g;
     LBM_HIP(hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0));
-    c->graph_parity = c->cur;
+    c->graph_parity = c->cur | (c->rho_idx << 1);
     c->graph_dirty = false;
     return LBM_OK;
 }
@@ -396,20 +419,34 @@ static int run_steps(lbm_ctx* c, int64_t nsteps) {
         if (rc != LBM_OK) return rc;
     }
     int64_t done = 0;
+    // D3Q19 sweeps that form the next step's density (PSUM variants)
+    const bool forms = c->Q == 19 && !c->is_batch && step3d_forms_density<real>(C, c->variant);
     if (c->graph_steps > 0 && nsteps >= c->graph_steps) {
-        if (c->graph_dirty || c->graph_parity != c->cur || !c->graph_exec) {
+        if (forms && !c->rho_valid) {
+            // the graph starts from a valid density: form it once here
+            Fields<real> F = make_fields<real>(c, c->cur);
+            LBM_HIP(launch_density3d<real>(C, F, c->stream));
+            c->rho_valid = true;
+        }
+        if (c->graph_dirty || c->graph_parity != (c->cur | (c->rho_idx << 1)) || !c->graph_exec) {
             int rc = capture_graph<real>(c, C);
             if (rc != LBM_OK) return rc;
         }
-        // an even number of steps per replay leaves the buffer parity as is
+        // an even number of steps per replay leaves the buffer parities as
+        // they are
         for (; nsteps - done >= c->graph_steps; done += c->graph_steps)
             LBM_HIP(hipGraphLaunch(c->graph_exec, c->stream));
+        if (done > 0 && c->Q == 19) c->rho_valid = forms;
     }
     for (; done < nsteps; ++done) {
-        hipError_t e = launch_one<real>(c, C, c->cur, c->stream);
+        hipError_t e = launch_one<real>(c, C, c->cur, c->stream, c->rho_idx, c->rho_valid);
         if (e != hipSuccess)
             return fail(LBM_EDEVICE, std::string("step launch: ") + hipGetErrorString(e));
         c->cur ^= 1;
+        if (c->Q == 19) {
+            if (forms) c->rho_idx ^= 1;
+            c->rho_valid = forms;
+        }
     }
     return LBM_OK;
 }
@@ -434,7 +471,7 @@ static Fields<real> case_fields(const lbm_ctx* c, const lbm_case& k) {
     F.phi = (const real*)c->phi + k.wall_off;
     F.drho = (const real*)c->drho + k.wall_off;
     F.flag = c->flag;
-    F.rho = (real*)c->rho;
+    F.rho = (real*)c->rho_buf[0];
     F.gfcode = c->gfcode;
     return F;
 }
@@ -828,8 +865,8 @@ int lbm_create(const lbm_params* p, void* stream, void* workspace, size_t ws_byt
         c->variant = p->precision == 4 ? tile2d_preferred_variant<float>()
                                        : tile2d_preferred_variant<double>();
     else
-        c->variant = p->precision == 4 ? step3d_preferred_variant<float>()
-                                       : step3d_preferred_variant<double>();
+        c->variant = p->precision == 4 ? step3d_preferred_variant<float>(p->nx, p->ny, p->nz)
+                                       : step3d_preferred_variant<double>(p->nx, p->ny, p->nz);
     if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
         lbm_destroy(c);  // releases whichever event was created
         return fail(LBM_EDEVICE, "hipEventCreate failed");
@@ -870,6 +907,7 @@ int lbm_set_geometry(lbm_ctx* c, const uint8_t* solid_host) {
     c->geom = std::move(g);
     c->have_geom = true;
     c->have_fields = false;
+    c->rho_valid = false;
     c->tw_dirty = true;
     c->scheme = LBM_WET_IVD;
     c->scalar = 0.0;
@@ -1037,6 +1075,7 @@ int lbm_set_fields(lbm_ctx* c, const void* rho_dev, const void* u_dev) {
     LBM_HIP(launch_fill_i32(c->flag, 0, 4, c->stream));
     c->have_fields = true;
     c->domain_error = false;
+    c->rho_valid = false;
     return LBM_OK;
 }
 
@@ -1057,6 +1096,7 @@ int lbm_set_state(lbm_ctx* c, const void* f_dev) {
     LBM_HIP(launch_fill_i32(c->flag, 0, 4, c->stream));
     c->have_fields = true;
     c->domain_error = false;
+    c->rho_valid = false;
     return LBM_OK;
 }
 
@@ -1235,6 +1275,7 @@ int lbm_autotune(lbm_ctx* c, int64_t steps, void* save_dev, int32_t* best_out,
     if (save_dev) {
         LBM_HIP(hipMemcpyAsync(c->f[c->cur], save_dev, fbytes, hipMemcpyDeviceToDevice, c->stream));
         LBM_HIP(hipStreamSynchronize(c->stream));
+        c->rho_valid = false;
     }
     c->variant = best;
     c->graph_dirty = true;

@@ -122,6 +122,12 @@ struct Fields {
     int32_t* flag;         // set to 1 when a psi argument is < 0 or NaN
     real* rho = nullptr;   // density of every node (0 off the fluid), written by
                            // the density pass that precedes a sweep step
+    // D3Q19 sweeps that also form the next step's density: rho already holds
+    // the density of fin (no density pass needed), rho_next receives that of
+    // fout, ring the per-block partial sums for the nodes around each block
+    bool rho_valid = false;
+    real* rho_next = nullptr;
+    real* ring = nullptr;
     // Per-tile wall lists of the D2Q9 tile step (improved virtual density):
     // tile t owns entries [t * tw_stride, (t + 1) * tw_stride); each entry
     // packs (wall count of the tile << 16) | LDS position of one wall node

@@ -105,7 +105,15 @@ struct lbm_ctx {
     int32_t* flag = nullptr;
     double* part = nullptr;
     double* diag_out = nullptr;
-    void* rho = nullptr;  // node densities written by the density pass (sweep kernels)
+    // node densities of the D3Q19 sweeps: rho_buf[rho_idx] is read by the
+    // next step; rho_valid when it already holds the density of the current
+    // state (formed by a step of a PSUM variant, or by a density pass since),
+    // so that the next step needs no density pass; rho_buf[rho_idx ^ 1]
+    // receives the density a PSUM step forms, with ring as its scratch
+    void* rho_buf[2] = {nullptr, nullptr};
+    int rho_idx = 0;
+    bool rho_valid = false;
+    void* ring = nullptr;
     int nparts = 0;
     int32_t* gfcode = nullptr;  // geometric-formulation stencil code per wall node
     // per-tile wall lists of the D2Q9 tile step (see Fields::tw_pack)

@@ -127,12 +127,18 @@ hipError_t launch_step2d_march(const Coef<real>& C, const Fields<real>& F, const
 template <typename real>
 int step3d_variants();
 template <typename real>
-int step3d_preferred_variant();
+int step3d_preferred_variant(int nx, int ny, int nz);
 template <typename real>
 int grid3d_blocks(int nx, int ny, int nz, int variant);
 template <typename real>
 hipError_t launch_step3d(const Coef<real>& C, const Fields<real>& F, const FieldOut<real>& O,
                          int mode, int variant, hipStream_t s);
+template <typename real>
+bool step3d_forms_density(const Coef<real>& C, int variant);
+template <typename real>
+size_t step3d_ring_elems(int nx, int ny, int nz);
+template <typename real>
+hipError_t launch_density3d(const Coef<real>& C, const Fields<real>& F, hipStream_t s);
 
 // discrete adjoint of the D2Q9 step (adjoint2d.hip)
 template <typename real>

@@ -101,14 +101,119 @@ static void launch_density(const Coef<real>& C, const Fields<real>& F, hipStream
                        C.ny, C.nz);
 }
 
+// Where a block keeps what its sources send to the nodes around it (its
+// part of Fd.ring, PsumFaces<TX, TY, TZ>::size values per block, block b at
+// b * size), by the node's position (i, j, k) relative to the block's
+// origin: the two faces below and above the block (k = -1, TZ) as
+// (TY + 2) x (TX + 2) planes, then the rows j = -1 and j = TY of the slices
+// 0 .. TZ - 1 (TX + 2 positions each), then the columns i = -1 and i = TX
+// of those slices (TY positions each).  Each kind is contiguous, so a pass
+// over one face reads neighbouring values.
+template <int TX, int TY, int TZ>
+struct PsumFaces {
+    static constexpr int ZF = (TY + 2) * (TX + 2), YF = TZ * (TX + 2), XF = TZ * TY;
+    static constexpr int size = 2 * ZF + 2 * YF + 2 * XF;
+    __device__ __forceinline__ static int index(int i, int j, int k) {
+        if (k < 0 || k >= TZ) return (k < 0 ? 0 : ZF) + (j + 1) * (TX + 2) + i + 1;
+        if (j < 0 || j >= TY) return 2 * ZF + (j < 0 ? 0 : YF) + k * (TX + 2) + i + 1;
+        return 2 * ZF + 2 * YF + (i < 0 ? 0 : XF) + k * TY + j;
+    }
+};
+
+// Completes the densities a PSUM sweep formed: a fluid node on a face of
+// its block adds the partial sums that the neighbouring blocks' sources
+// sent to it.  The blocks that can send to it are those across the faces it
+// lies on (f = -1 / +1 along an axis where it sits on the low / high face)
+// and across the edges between two of those faces; D3Q19 has no velocity
+// along a body diagonal, so the block across a corner sends nothing.  The
+// six candidates are read unconditionally (a candidate that does not apply
+// reads the block's first value and adds 0), so the loads of a wave are in
+// flight together.  The offset of the neighbour (not its absolute position)
+// locates the node in the neighbour's part, so a block that is its own
+// periodic neighbour is handled too.
+template <typename real, int TX, int TY, int TZ>
+__global__ __launch_bounds__(256) void k_psum_close(const uint8_t* __restrict__ cls,
+                                                    real* __restrict__ rho,
+                                                    const real* __restrict__ ring, int na, int nb,
+                                                    int nc) {
+    static_assert(TX > 2 && TY > 2 && TZ > 2, "a block has interior nodes along every axis");
+    using PF = PsumFaces<TX, TY, TZ>;
+    // one thread per face node: per block the two z faces (TX x TY), the
+    // two y faces without their z edges (TX x (TZ - 2)), then the two x
+    // faces without either (TY - 2) x (TZ - 2)
+    constexpr int ZF = TX * TY, YF = TX * (TZ - 2), XF = (TY - 2) * (TZ - 2);
+    constexpr uint32_t FPB = 2 * ZF + 2 * YF + 2 * XF;
+    const int gx = na / TX, gy = nb / TY, gz = nc / TZ;
+    const uint32_t t = blockIdx.x * 256u + threadIdx.x;
+    if (t >= (uint32_t)gx * (uint32_t)gy * (uint32_t)gz * FPB) return;
+    const uint32_t b = t / FPB;
+    int q = (int)(t - b * FPB), i, j, k;
+    if (q < 2 * ZF) {
+        k = q < ZF ? 0 : TZ - 1;
+        q = q < ZF ? q : q - ZF;
+        i = q % TX;
+        j = q / TX;
+    } else if ((q -= 2 * ZF) < 2 * YF) {
+        j = q < YF ? 0 : TY - 1;
+        q = q < YF ? q : q - YF;
+        i = q % TX;
+        k = 1 + q / TX;
+    } else {
+        q -= 2 * YF;
+        i = q < XF ? 0 : TX - 1;
+        q = q < XF ? q : q - XF;
+        j = 1 + q % (TY - 2);
+        k = 1 + q / (TY - 2);
+    }
+    const int bx = (int)(b % (uint32_t)gx), by = (int)((b / (uint32_t)gx) % (uint32_t)gy);
+    const int bz = (int)(b / ((uint32_t)gx * (uint32_t)gy));
+    const int fx = i == 0 ? -1 : (i == TX - 1 ? 1 : 0);
+    const int fy = j == 0 ? -1 : (j == TY - 1 ? 1 : 0);
+    const int fz = k == 0 ? -1 : (k == TZ - 1 ? 1 : 0);
+    const uint32_t n = ((uint32_t)(bz * TZ + k) * (uint32_t)nb + (uint32_t)(by * TY + j)) *
+                           (uint32_t)na + (uint32_t)(bx * TX + i);
+    auto wrap1 = [](int v, int m) { return v < 0 ? v + m : (v >= m ? v - m : v); };
+    const int ox[6] = {fx, 0, 0, fx, fx, 0};
+    const int oy[6] = {0, fy, 0, fy, 0, fy};
+    const int oz[6] = {0, 0, fz, 0, fz, fz};
+    real v[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        const bool use = (c < 3) ? ((ox[c] | oy[c] | oz[c]) != 0)
+                                 : (c == 3 ? (fx != 0 && fy != 0)
+                                           : (c == 4 ? (fx != 0 && fz != 0) : (fy != 0 && fz != 0)));
+        const int nbx = wrap1(bx + ox[c], gx), nby = wrap1(by + oy[c], gy),
+                  nbz = wrap1(bz + oz[c], gz);
+        const size_t at = (size_t)(nbx + gx * (nby + gy * nbz)) * PF::size +
+                          PF::index(i - ox[c] * TX, j - oy[c] * TY, k - oz[c] * TZ);
+        v[c] = ring[use ? at : (size_t)0];
+        v[c] = use ? v[c] : real(0);
+    }
+    const uint8_t cl = cls[n];
+    real r = rho[n];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) r += v[c];
+    if (cl == CLS_FLUID) rho[n] = r;
+}
+
 // FUSED: no density pass.  Phase A loads the populations of its slice,
 // sums the density of every node of the slice (owned and halo) itself and
 // keeps the owned node's populations in registers until phase C collides
 // them two iterations later (a ring of three register sets, so the loop
 // body is instantiated three times with the sets rotated).
 // OCC: minimum waves per SIMD asked of the register allocator.
+// PSUM (D3Q19, step mode): the sweep also forms the density of the next
+// step.  After a slice collides, its post-collision populations are staged
+// in LDS and every owned position, and every position of the 1-node ring
+// around the cross-section, adds the ones that stream to it (from the
+// slices below, at and above); the owned node's own bounce-backs add to
+// its own density.  A node whose sources all lie in the block gets its
+// whole density; the others get a partial sum, and the block writes what
+// its sources send to the nodes around it into its part of Fd.ring (laid
+// out as PsumFaces describes).  k_psum_close then adds those to the nodes
+// on block faces.  Needs no ragged block.
 template <typename L, typename real, int TX, int TY, int TZ, int MODE, bool XCD, bool BUF,
-          bool FUSED = false, int OCC = 1>
+          bool FUSED = false, int OCC = 1, bool PSUM = false>
 __global__ __launch_bounds__(TX* TY, OCC) void k_step_march(Coef<real> C, Fields<real> Fd,
                                                             FieldOut<real> Out) {
     constexpr bool D3 = (L::D == 3);
@@ -125,6 +230,14 @@ __global__ __launch_bounds__(TX* TY, OCC) void k_step_march(Coef<real> C, Fields
     __shared__ uint8_t s_cls[NSLOT][PS];
     __shared__ real s_rho[NSLOT][PS];
     __shared__ real s_psi[NPSI][PS];
+    static_assert(!PSUM || (D3 && !FUSED && MODE == MODE_STEP), "PSUM: D3Q19 step sweep");
+    constexpr int NRING = 2 * (TX + 2) + 2 * TY;  // the 1-node ring around the cross-section
+    static_assert(!PSUM || NRING <= NT, "one ring position per thread");
+    using PF = PsumFaces<TX, TY, TZ>;
+    // staged populations on the cross-section with a zero border two nodes
+    // wide, so that every read of the gather stays in the array
+    constexpr int SW = TX + 4, SS = (TX + 4) * (TY + 4);
+    __shared__ real s_fs[PSUM ? Q : 1][PSUM ? SS : 1];
 
     const int na = C.nx;
     const int nb = D3 ? C.ny : 1;
@@ -179,6 +292,65 @@ __global__ __launch_bounds__(TX* TY, OCC) void k_step_march(Coef<real> C, Fields
         ring_ab[jj] = (uint32_t)ring_y[jj] * na + ring_x[jj];
     }
 
+    // PSUM: this thread's ring position (i, j) around the cross-section
+    // (rows below and above, then the columns left and right), and the
+    // partial densities of the target slices cc - 1, cc, cc + 1 of the
+    // owned position (acc) and of the ring position (racc)
+    int ring_i = 0, ring_j = 0;
+    if (PSUM && tid < NRING) {
+        if (tid < TX + 2) {
+            ring_i = tid - 1;
+            ring_j = -1;
+        } else if (tid < 2 * (TX + 2)) {
+            ring_i = tid - (TX + 2) - 1;
+            ring_j = TY;
+        } else {
+            const int k = tid - 2 * (TX + 2);
+            ring_j = k / 2;
+            ring_i = (k & 1) ? TX : -1;
+        }
+    }
+    real acc[3] = {real(0), real(0), real(0)}, racc[3] = {real(0), real(0), real(0)};
+    const size_t box0 = (size_t)(bx + gridDim.x * (by + gridDim.y * bz)) * PF::size;
+    auto box_at = [&](int k, int j, int i) { return box0 + (size_t)PF::index(i, j, k); };
+    // sum of the staged populations that stream to in-plane position (i, j)
+    // from the slice cc, split by the slice they reach (non-fluid and
+    // outside positions hold 0)
+    auto gather = [&](int i, int j, real (&a3)[3]) __attribute__((always_inline)) {
+        const int q = (j + 2) * SW + i + 2;
+#pragma unroll
+        for (int b = 0; b < Q; ++b) a3[L::ez[b] + 1] += s_fs[b][q - L::ex[b] - L::ey[b] * SW];
+    };
+    if constexpr (PSUM) {
+        for (int e = tid; e < Q * SS; e += NT) (&s_fs[0][0])[e] = real(0);
+        // (the first barrier of the sweep orders these before any use)
+    }
+
+    // PSUM phase D for the slice cc_ collided last (staged in s_fs): its
+    // contributions to the slices around it, then the slice below it is
+    // complete for this block.  Runs after the barrier that follows the next
+    // phase A, so it needs no barrier of its own; the classes of the slice
+    // below are in ring slot sl_below.
+    auto psum_phase = [&](int cc_, int sl_below) __attribute__((always_inline)) {
+        const int oi = tid % TX, oj = tid / TX;
+        gather(oi, oj, acc);
+        if (tid < NRING) gather(ring_i, ring_j, racc);
+        const int t = cc_ - 1;
+        if (t >= c0) {
+            Fd.rho_next[(uint32_t)t * nab + own_ab] =
+                (s_cls[sl_below][own_p] == CLS_FLUID) ? acc[0] : real(0);
+        } else {
+            Fd.ring[box_at(-1, oj, oi)] = acc[0];  // the face below the block
+        }
+        if (tid < NRING) Fd.ring[box_at(t - c0, ring_j, ring_i)] = racc[0];
+        acc[0] = acc[1];
+        acc[1] = acc[2];
+        acc[2] = real(0);
+        racc[0] = racc[1];
+        racc[1] = racc[2];
+        racc[2] = real(0);
+    };
+
     bool bad = false;
     double d_sum = 0.0;
     real d_umax = real(0), d_rmin = real(1e30), d_rmax = real(-1e30);
@@ -232,6 +404,10 @@ __global__ __launch_bounds__(TX* TY, OCC) void k_step_march(Coef<real> C, Fields
             }
         }
         __syncthreads();
+        // ---------------- D (PSUM) of the slice collided in the previous iteration
+        if constexpr (PSUM) {
+            if (it >= 5) psum_phase(c0 - 5 + it, (it - 4) % NSLOT);
+        }
         // ---------------- B: psi (and wall densities) of slice c0 - 3 + it
         if (it >= 2) {
             const int sc = (it - 1) % NSLOT;
@@ -296,6 +472,12 @@ __global__ __launch_bounds__(TX* TY, OCC) void k_step_march(Coef<real> C, Fields
                     if (Out.rho) Out.rho[n] = (c == CLS_WALL) ? s_rho[sc][own_p] : real(0);
                     if (Out.u)
                         for (int d = 0; d < L::D; ++d) Out.u[(size_t)d * N + n] = real(0);
+                }
+                if constexpr (PSUM) {
+                    // a non-fluid position sends nothing
+                    const int q = (tid / TX + 2) * SW + tid % TX + 2;
+#pragma unroll
+                    for (int a = 0; a < Q; ++a) s_fs[a][q] = real(0);
                 }
             } else {
                 const real rho = s_rho[sc][own_p];
@@ -377,6 +559,7 @@ __global__ __launch_bounds__(TX* TY, OCC) void k_step_march(Coef<real> C, Fields
                     real fs[Q], u[3];
                     collide<L, real>(C, fl, rho, F, Fm, psi_c, fs, u);
                     const int ga = own_a, gb = D3 ? own_b : 0;
+                    real bsum = real(0);  // PSUM: bounce-backs return to this node
 #pragma unroll
                     for (int a = 0; a < Q; ++a) {
                         const int ea = L::ex[a];
@@ -394,11 +577,18 @@ __global__ __launch_bounds__(TX* TY, OCC) void k_step_march(Coef<real> C, Fields
                             // own slot; a wall neighbour also gets the bounce-back
                             io.st_nt(a, n, fs[a]);
                             if (!fluid_to) io.st(L::opp[a], t, fs[a]);
+                            if (PSUM && !fluid_to) bsum += fs[a];
                         } else if (fluid_to) {
                             io.st(a, t, fs[a]);
                         } else {
                             io.st(L::opp[a], n, fs[a]);
                         }
+                    }
+                    if constexpr (PSUM) {
+                        const int q = (tid / TX + 2) * SW + tid % TX + 2;
+#pragma unroll
+                        for (int a = 0; a < Q; ++a) s_fs[a][q] = fs[a];
+                        acc[1] += bsum;
                     }
                 }
             }
@@ -416,6 +606,21 @@ __global__ __launch_bounds__(TX* TY, OCC) void k_step_march(Coef<real> C, Fields
     } else {
         real R0[Q];
         for (int it = 0; it < TZ + 4; ++it) body(it, R0, R0);
+    }
+    if constexpr (PSUM) {
+        // phase D of the last slice, then the top slice of the chunk (partial)
+        // and the face above the block
+        __syncthreads();
+        psum_phase(c0 + TZ - 1, TZ % NSLOT);
+        const int oi = tid % TX, oj = tid / TX;
+        const int st = (TZ + 1) % NSLOT;  // classes of slice c0 + TZ - 1
+        Fd.rho_next[(uint32_t)(c0 + TZ - 1) * nab + own_ab] =
+            (s_cls[st][own_p] == CLS_FLUID) ? acc[0] : real(0);
+        Fd.ring[box_at(TZ, oj, oi)] = acc[1];
+        if (tid < NRING) {
+            Fd.ring[box_at(TZ - 1, ring_j, ring_i)] = racc[0];
+            Fd.ring[box_at(TZ, ring_j, ring_i)] = racc[1];
+        }
     }
 
     if (MODE == MODE_FIELDS && Out.part) {
@@ -600,28 +805,36 @@ struct Shape3D {
     bool fused;  // densities summed in the sweep (no density pass)
     int occ;     // minimum waves per SIMD asked of the register allocator
     bool brick;  // k_step_brick: no march, TZ slices per thread
+    bool psum = false;  // the sweep forms the next step's density (no density pass)
 };
 
 template <typename real>
 struct Variants3D;
 template <>
 struct Variants3D<float> {
-    static constexpr int count = 10;
+    static constexpr int count = 14;
     static constexpr int preferred = 2;  // 32 x 8 cross-section, chunks of 8 slices
+    // on lattices its blocks tile: the 32 x 8 x 32 sweep that forms the next
+    // density (0.730 ms against 0.815 ms for a step on the 256^3 sphere)
+    static constexpr int preferred_psum = 12;
     static constexpr Shape3D shape[count] = {
         {32, 8, 16, true, false, 1, false}, {32, 8, 16, false, false, 1, false},
         {32, 8, 8, true, false, 1, false},  {32, 8, 32, true, false, 1, false},
         {16, 16, 16, true, false, 1, false}, {32, 8, 16, true, true, 1, false},
         {32, 8, 32, true, true, 1, false},  {32, 8, 2, true, false, 1, true},
-        {64, 4, 16, true, false, 1, false}, {256, 2, 16, true, false, 1, false}};
+        {64, 4, 16, true, false, 1, false}, {256, 2, 16, true, false, 1, false},
+        {32, 8, 8, true, false, 1, false, true}, {32, 8, 16, true, false, 1, false, true},
+        {32, 8, 32, true, false, 1, false, true}, {32, 8, 8, true, false, 4, false, true}};
 };
 template <>
 struct Variants3D<double> {
-    static constexpr int count = 4;
+    static constexpr int count = 5;
     static constexpr int preferred = 3;  // the brick: 1.63 ms against 1.76 ms on the 256^3 sphere
+    static constexpr int preferred_psum = -1;
     static constexpr Shape3D shape[count] = {
         {32, 8, 16, true, false, 1, false}, {32, 8, 16, false, false, 1, false},
-        {32, 8, 16, true, true, 1, false}, {32, 8, 2, true, false, 1, true}};
+        {32, 8, 16, true, true, 1, false}, {32, 8, 2, true, false, 1, true},
+        {32, 8, 16, true, false, 1, false, true}};
 };
 
 template <typename real>
@@ -629,9 +842,20 @@ int step3d_variants() {
     return Variants3D<real>::count;
 }
 
+template <typename real>
+static bool psum_applies(const Coef<real>& C, const Shape3D& sh);
+
 // the variant a D3Q19 context starts with (fastest on the 256^3 benchmark)
 template <typename real>
-int step3d_preferred_variant() {
+int step3d_preferred_variant(int nx, int ny, int nz) {
+    constexpr int v = Variants3D<real>::preferred_psum;
+    if constexpr (v >= 0) {
+        Coef<real> C{};
+        C.nx = nx;
+        C.ny = ny;
+        C.nz = nz;
+        if (psum_applies(C, Variants3D<real>::shape[v])) return v;
+    }
     return Variants3D<real>::preferred;
 }
 
@@ -641,18 +865,45 @@ int grid3d_blocks(int nx, int ny, int nz, int variant) {
     return ((nx + s.TX - 1) / s.TX) * ((ny + s.TY - 1) / s.TY) * ((nz + s.TZ - 1) / s.TZ);
 }
 
+// a PSUM variant forms the next density only on lattices its blocks tile
+// exactly (otherwise it runs as the plain sweep of its shape)
+template <typename real>
+static bool psum_applies(const Coef<real>& C, const Shape3D& sh) {
+    return sh.psum && C.nx % sh.TX == 0 && C.ny % sh.TY == 0 && C.nz % sh.TZ == 0 &&
+           (uint64_t)19 * (uint64_t)C.nx * C.ny * C.nz * sizeof(real) <= 0xFFFFFFFFull;
+}
+
 template <typename real, int V, int MODE, bool BUF = true>
 static void launch_v3(const Coef<real>& C, const Fields<real>& F, const FieldOut<real>& O,
                       hipStream_t s) {
     constexpr Shape3D sh = Variants3D<real>::shape[V];
     dim3 grid((C.nx + sh.TX - 1) / sh.TX, (C.ny + sh.TY - 1) / sh.TY, (C.nz + sh.TZ - 1) / sh.TZ);
-    if constexpr (sh.brick && MODE == MODE_STEP && BUF)
+    if constexpr (sh.brick && MODE == MODE_STEP && BUF) {
         hipLaunchKernelGGL((k_step_brick<real, sh.TX, sh.TY, sh.TZ, sh.xcd>), grid,
                            dim3(sh.TX * sh.TY), 0, s, C, F);
-    else
+    } else if constexpr (sh.psum && MODE == MODE_STEP && BUF) {
+        if (psum_applies(C, sh)) {
+            hipLaunchKernelGGL(
+                (k_step_march<D3Q19, real, sh.TX, sh.TY, sh.TZ, MODE_STEP, sh.xcd, true, false,
+                              sh.occ, true>),
+                grid, dim3(sh.TX * sh.TY), 0, s, C, F, O);
+            constexpr uint32_t fpb = 2 * sh.TX * sh.TY + 2 * sh.TX * (sh.TZ - 2) +
+                                     2 * (sh.TY - 2) * (sh.TZ - 2);
+            const uint32_t faces = (uint32_t)(C.nx / sh.TX) * (uint32_t)(C.ny / sh.TY) *
+                                   (uint32_t)(C.nz / sh.TZ) * fpb;
+            hipLaunchKernelGGL((k_psum_close<real, sh.TX, sh.TY, sh.TZ>),
+                               dim3((faces + 255) / 256), dim3(256), 0, s, F.cls, F.rho_next,
+                               F.ring, C.nx, C.ny, C.nz);
+        } else {
+            hipLaunchKernelGGL((k_step_march<D3Q19, real, sh.TX, sh.TY, sh.TZ, MODE_STEP, sh.xcd,
+                                             true, false, sh.occ>),
+                               grid, dim3(sh.TX * sh.TY), 0, s, C, F, O);
+        }
+    } else {
         hipLaunchKernelGGL(
             (k_step_march<D3Q19, real, sh.TX, sh.TY, sh.TZ, MODE, sh.xcd, BUF, sh.fused, sh.occ>),
             grid, dim3(sh.TX * sh.TY), 0, s, C, F, O);
+    }
 }
 
 template <typename real, size_t... I>
@@ -662,6 +913,39 @@ static auto table_v3(std::index_sequence<I...>) {
     return std::array<Fn, sizeof...(I)>{&launch_v3<real, (int)I, MODE_STEP>...};
 }
 
+// whether a step of this variant leaves the density of its output state in
+// Fd.rho_next (a PSUM sweep on a lattice its blocks tile)
+template <typename real>
+bool step3d_forms_density(const Coef<real>& C, int variant) {
+    if (variant < 0 || variant >= Variants3D<real>::count) return false;
+    return psum_applies(C, Variants3D<real>::shape[variant]);
+}
+
+// elements of the per-block partial-sum boxes the PSUM variants need (the
+// largest over those variants; 0 when none applies to the lattice)
+template <typename real>
+size_t step3d_ring_elems(int nx, int ny, int nz) {
+    size_t m = 0;
+    for (int v = 0; v < Variants3D<real>::count; ++v) {
+        const Shape3D sh = Variants3D<real>::shape[v];
+        if (!sh.psum || nx % sh.TX || ny % sh.TY || nz % sh.TZ) continue;
+        const size_t e = (size_t)(nx / sh.TX) * (ny / sh.TY) * (nz / sh.TZ) *
+                         (size_t)(2 * (sh.TY + 2) * (sh.TX + 2) + 2 * sh.TZ * (sh.TX + 2) +
+                                  2 * sh.TZ * sh.TY);
+        m = e > m ? e : m;
+    }
+    return m;
+}
+
+// the density pass alone, into Fd.rho (the density of Fd.fin)
+template <typename real>
+hipError_t launch_density3d(const Coef<real>& C, const Fields<real>& F, hipStream_t s) {
+    launch_density<D3Q19, real>(C, F, s);
+    return hipGetLastError();
+}
+
+// Fd.rho_valid: Fd.rho already holds the density of Fd.fin, so the density
+// pass is skipped (the density a PSUM step formed, or one computed since)
 template <typename real>
 hipError_t launch_step3d(const Coef<real>& C, const Fields<real>& F, const FieldOut<real>& O,
                          int mode, int variant, hipStream_t s) {
@@ -669,17 +953,18 @@ hipError_t launch_step3d(const Coef<real>& C, const Fields<real>& F, const Field
     if (variant < 0 || variant >= Variants3D<real>::count) return hipErrorInvalidValue;
     // population arrays of 4 GiB or more cannot use 32-bit buffer offsets
     if ((uint64_t)19 * (uint64_t)C.nx * C.ny * C.nz * sizeof(real) > 0xFFFFFFFFull) {
-        launch_density<D3Q19, real>(C, F, s);
+        if (!F.rho_valid) launch_density<D3Q19, real>(C, F, s);
         if (mode == MODE_STEP) launch_v3<real, 0, MODE_STEP, false>(C, F, O, s);
         else launch_v3<real, 0, MODE_FIELDS, false>(C, F, O, s);
         return hipGetLastError();
     }
     if (mode == MODE_FIELDS) {
-        launch_density<D3Q19, real>(C, F, s);
+        if (!F.rho_valid) launch_density<D3Q19, real>(C, F, s);
         launch_v3<real, 0, MODE_FIELDS>(C, F, O, s);
         return hipGetLastError();
     }
-    if (!Variants3D<real>::shape[variant].fused) launch_density<D3Q19, real>(C, F, s);
+    if (!Variants3D<real>::shape[variant].fused && !F.rho_valid)
+        launch_density<D3Q19, real>(C, F, s);
     static const auto tab = table_v3<real>(std::make_index_sequence<Variants3D<real>::count>{});
     tab[variant](C, F, O, s);
     return hipGetLastError();
@@ -748,17 +1033,32 @@ template hipError_t launch_step2d_march<double>(const Coef<double>&, const Field
 #endif
 #if LBM_PREC != 8
 template int step3d_variants<float>();
-template int step3d_preferred_variant<float>();
+template int step3d_preferred_variant<float>(int, int, int);
 #endif
 #if LBM_PREC != 4
 template int step3d_variants<double>();
-template int step3d_preferred_variant<double>();
+template int step3d_preferred_variant<double>(int, int, int);
 #endif
 #if LBM_PREC != 8
 template int grid3d_blocks<float>(int, int, int, int);
 #endif
 #if LBM_PREC != 4
 template int grid3d_blocks<double>(int, int, int, int);
+#endif
+#if LBM_PREC != 8
+template size_t step3d_ring_elems<float>(int, int, int);
+#endif
+#if LBM_PREC != 4
+template size_t step3d_ring_elems<double>(int, int, int);
+#endif
+#if LBM_PREC != 8
+template bool step3d_forms_density<float>(const Coef<float>&, int);
+template hipError_t launch_density3d<float>(const Coef<float>&, const Fields<float>&, hipStream_t);
+#endif
+#if LBM_PREC != 4
+template bool step3d_forms_density<double>(const Coef<double>&, int);
+template hipError_t launch_density3d<double>(const Coef<double>&, const Fields<double>&,
+                                             hipStream_t);
 #endif
 #if LBM_PREC != 8
 template hipError_t launch_step3d<float>(const Coef<float>&, const Fields<float>&,

@@ -246,7 +246,7 @@ def test_every_d2q9_variant(oracle_mod, gpu_lib, precision, variant):
 
 
 @pytest.mark.parametrize("precision", [8, 4])
-@pytest.mark.parametrize("variant", range(10))
+@pytest.mark.parametrize("variant", range(16))
 def test_every_d3q19_variant(oracle_mod, gpu_lib, precision, variant):
     if variant >= _nvariants(19, precision):
         pytest.skip("no such variant")
