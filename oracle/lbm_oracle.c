@@ -165,6 +165,8 @@ static int check_params(const orc_params* p) {
     if (p->lattice == 9 && p->nz != 1) return ORC_EINVAL;
     if (p->scheme < ORC_IVD || p->scheme > ORC_GF) return ORC_EINVAL;
     if (p->scheme == ORC_GF && p->lattice != 9) return ORC_EINVAL;  /* 2-D scheme */
+    if (p->sfi_solid_psi < 0 || p->sfi_solid_psi > 4) return ORC_EINVAL;
+    if (p->sfi_psi_presum != 0 && p->sfi_psi_presum != 1) return ORC_EINVAL;
     return ORC_OK;
 }
 
@@ -563,9 +565,28 @@ static int macro_phases(const orc_params* p, const lat_t* L, const geom_t* g,
             w->rho[b] = p->rho_w;
             if (psi_of(p, p->rho_w, &w->psi[b]) != ORC_OK) return ORC_EDOMAIN;
         } else {
-            /* solid-fluid interaction: the solid carries no pseudopotential */
+            /* solid-fluid interaction: the solid carries no pseudopotential
+             * (the other values of sfi_solid_psi are alternative readings) */
             w->rho[b] = 0.0;
             w->psi[b] = 0.0;
+            real rs = 0.0;
+            if (p->sfi_solid_psi == 1) {
+                real num = 0.0;
+                double den = 0.0;
+                for (int a = 1; a < Q; ++a) {
+                    int64_t y = nbr(p, b, &L->e[3 * a]);
+                    if (!solid[y]) {
+                        num += L->w[a] * w->rho[y];
+                        den += L->w[a];
+                    }
+                }
+                rs = num / den;
+            } else if (p->sfi_solid_psi == 2) {
+                rs = p->rho_g;
+            } else if (p->sfi_solid_psi == 3) {
+                rs = p->rho_l;
+            }
+            if (RE(rs) > 0.0 && psi_of(p, rs, &w->psi[b]) != ORC_OK) return ORC_EDOMAIN;
         }
     }
 
@@ -579,16 +600,19 @@ static int macro_phases(const orc_params* p, const lat_t* L, const geom_t* g,
         if (solid[n]) continue;
         real sm[3] = {0.0, 0.0, 0.0};
         double sa[3] = {0.0, 0.0, 0.0};
+        const int own = p->scheme == ORC_SFI && p->sfi_solid_psi == 4;
         for (int a = 1; a < Q; ++a) {
             int64_t y = nbr(p, n, &L->e[3 * a]);
+            real psy = (own && solid[y]) ? w->psi[n] : w->psi[y];
             for (int d = 0; d < D; ++d) {
-                sm[d] += L->w[a] * w->psi[y] * (double)L->e[3 * a + d];
+                sm[d] += L->w[a] * psy * (double)L->e[3 * a + d];
                 if (solid[y]) sa[d] += L->w[a] * (double)L->e[3 * a + d];
             }
         }
         for (int d = 0; d < D; ++d) {
             real fm = -p->G * w->psi[n] * sm[d];
-            real fa = (p->scheme == ORC_SFI) ? -p->G_w * w->rho[n] * sa[d] : 0.0;
+            real pre = p->sfi_psi_presum ? w->psi[n] : w->rho[n];
+            real fa = (p->scheme == ORC_SFI) ? -p->G_w * pre * sa[d] : 0.0;
             w->Fm[d * N + n] = fm;
             w->F[d * N + n] = fm + fa + p->body_force[d];
         }

@@ -45,6 +45,15 @@ typedef struct {
     double rho_w;           /* VD constant virtual density */
     double G_w;             /* SFI adhesion strength (Eq. 8) */
     double rho_g, rho_l;    /* limiter bounds of the improved scheme */
+    /* SFI only: the pseudopotential the solid nodes carry in Eq. 5, which
+     * the paper does not state.  0: none (the reading the library takes);
+     * 1: psi of the Eq. 17 mean of the node's fluid neighbours; 2: psi(rho_g);
+     * 3: psi(rho_l); 4: each fluid node sees its solid neighbours at its own
+     * psi.  Values 1-4 exist for the study of Fig. 6 only. */
+    int32_t sfi_solid_psi;
+    /* SFI only: pre-sum factor of Eq. 8; 0: rho(x) as printed, 1: psi(x)
+     * (for the same study) */
+    int32_t sfi_psi_presum;
 } orc_params;
 
 /* ---- thermodynamics (real arithmetic) ---- */
