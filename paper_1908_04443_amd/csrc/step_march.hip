@@ -234,10 +234,20 @@ __global__ __launch_bounds__(TX* TY, OCC) void k_step_march(Coef<real> C, Fields
     constexpr int NRING = 2 * (TX + 2) + 2 * TY;  // the 1-node ring around the cross-section
     static_assert(!PSUM || NRING <= NT, "one ring position per thread");
     using PF = PsumFaces<TX, TY, TZ>;
-    // staged populations on the cross-section with a zero border two nodes
-    // wide, so that every read of the gather stays in the array
-    constexpr int SW = TX + 4, SS = (TX + 4) * (TY + 4);
-    __shared__ real s_fs[PSUM ? Q : 1][PSUM ? SS : 1];
+    // staged post-collision populations of the slice on the cross-section
+    // with a zero border one node wide, slot after slot, and SPAD zeros
+    // before the first slot and after the last.  A source two nodes outside
+    // the cross-section (a ring position's) then falls on the border of the
+    // row beside it or on the padding: every read is in the array and reads
+    // 0 for a source outside the block.  Only the 16 velocities that move in
+    // the cross-section are staged (slot SLOT[a]); the rest velocity and +-z
+    // stay in their column and go straight into the owned node's sums.
+    constexpr int SW = TX + 2, SS = (TX + 2) * (TY + 2), QS = 16, SPAD = SW + 1;
+    constexpr int SLOT[19] = {-1, 0, 1, 2, 3, -1, -1, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15};
+    static_assert(!PSUM || (L::ex[5] == 0 && L::ey[5] == 0 && L::ez[5] == 1 && L::ex[6] == 0 &&
+                            L::ey[6] == 0 && L::ez[6] == -1),
+                  "velocities 5 and 6 are +z and -z");
+    __shared__ real s_fs[PSUM ? QS * SS + 2 * SPAD : 1];
 
     const int na = C.nx;
     const int nb = D3 ? C.ny : 1;
@@ -313,16 +323,17 @@ __global__ __launch_bounds__(TX* TY, OCC) void k_step_march(Coef<real> C, Fields
     real acc[3] = {real(0), real(0), real(0)}, racc[3] = {real(0), real(0), real(0)};
     const size_t box0 = (size_t)(bx + gridDim.x * (by + gridDim.y * bz)) * PF::size;
     auto box_at = [&](int k, int j, int i) { return box0 + (size_t)PF::index(i, j, k); };
-    // sum of the staged populations that stream to in-plane position (i, j)
-    // from the slice cc, split by the slice they reach (non-fluid and
-    // outside positions hold 0)
-    auto gather = [&](int i, int j, real (&a3)[3]) __attribute__((always_inline)) {
-        const int q = (j + 2) * SW + i + 2;
+    // sum of the staged populations that stream to in-plane position q =
+    // (j + 1) SW + i + 1 from the slice cc, split by the slice they reach
+    // (non-fluid and outside positions hold 0)
+    auto gather = [&](int q, real (&a3)[3]) __attribute__((always_inline)) {
 #pragma unroll
-        for (int b = 0; b < Q; ++b) a3[L::ez[b] + 1] += s_fs[b][q - L::ex[b] - L::ey[b] * SW];
+        for (int b = 0; b < Q; ++b)
+            if (SLOT[b] >= 0)
+                a3[L::ez[b] + 1] += s_fs[SPAD + SLOT[b] * SS + q - L::ex[b] - L::ey[b] * SW];
     };
     if constexpr (PSUM) {
-        for (int e = tid; e < Q * SS; e += NT) (&s_fs[0][0])[e] = real(0);
+        for (int e = tid; e < QS * SS + 2 * SPAD; e += NT) s_fs[e] = real(0);
         // (the first barrier of the sweep orders these before any use)
     }
 
@@ -333,8 +344,8 @@ __global__ __launch_bounds__(TX* TY, OCC) void k_step_march(Coef<real> C, Fields
     // below are in ring slot sl_below.
     auto psum_phase = [&](int cc_, int sl_below) __attribute__((always_inline)) {
         const int oi = tid % TX, oj = tid / TX;
-        gather(oi, oj, acc);
-        if (tid < NRING) gather(ring_i, ring_j, racc);
+        gather((oj + 1) * SW + oi + 1, acc);
+        if (tid < NRING) gather((ring_j + 1) * SW + ring_i + 1, racc);
         const int t = cc_ - 1;
         if (t >= c0) {
             Fd.rho_next[(uint32_t)t * nab + own_ab] =
@@ -357,7 +368,8 @@ __global__ __launch_bounds__(TX* TY, OCC) void k_step_march(Coef<real> C, Fields
     int d_cnt = 0;
 
     // Rl: populations of the owned node of slice c0 - 2 + it (fused only);
-    // Rc: those of slice c0 - 4 + it, loaded two iterations earlier
+    // Rc: those of slice c0 - 4 + it, loaded two iterations earlier (fused)
+    // or in phase A of this iteration
     auto body = [&](const int it, real (&Rl)[Q], real (&Rc)[Q]) __attribute__((always_inline)) {
         // ---------------- A: slice c0 - 2 + it
         {
@@ -391,6 +403,18 @@ __global__ __launch_bounds__(TX* TY, OCC) void k_step_march(Coef<real> C, Fields
                     s_rho[slot][ring_p[0]] = rc == CLS_FLUID ? rr : real(0);
                 }
             } else {
+                // the owned node's populations of the slice phase C collides
+                // in this iteration (its class arrived two iterations ago):
+                // issued here, so that the barriers and phase B cover their
+                // latency
+                const int ccA = c0 - 4 + it;
+                if (it >= 4 && ccA < nc && own_in &&
+                    s_cls[(it - 2) % NSLOT][own_p] == CLS_FLUID) {
+#pragma unroll
+                    for (int a = 0; a < Q; ++a)
+                        Rc[a] = io.ld(a, PULL ? up_node<L>(a, own_a, own_b, ccA, na, nb, nc, nab)
+                                              : (uint32_t)ccA * nab + own_ab);
+                }
                 // densities come from the density pass: one value per node
                 s_cls[slot][own_p] = Fd.cls[base + own_ab];
                 s_rho[slot][own_p] = Fd.rho[base + own_ab];
@@ -475,9 +499,9 @@ __global__ __launch_bounds__(TX* TY, OCC) void k_step_march(Coef<real> C, Fields
                 }
                 if constexpr (PSUM) {
                     // a non-fluid position sends nothing
-                    const int q = (tid / TX + 2) * SW + tid % TX + 2;
+                    const int q = (tid / TX + 1) * SW + tid % TX + 1;
 #pragma unroll
-                    for (int a = 0; a < Q; ++a) s_fs[a][q] = real(0);
+                    for (int a = 0; a < QS; ++a) s_fs[SPAD + a * SS + q] = real(0);
                 }
             } else {
                 const real rho = s_rho[sc][own_p];
@@ -521,9 +545,7 @@ __global__ __launch_bounds__(TX* TY, OCC) void k_step_march(Coef<real> C, Fields
                 }
                 real fl[Q];
 #pragma unroll
-                for (int a = 0; a < Q; ++a)
-                    fl[a] = FUSED ? Rc[a]
-                                  : io.ld(a, PULL ? up_node<L>(a, own_a, own_b, cc, na, nb, nc, nab) : n);
+                for (int a = 0; a < Q; ++a) fl[a] = Rc[a];
                 if (MODE == MODE_FIELDS) {
                     real j[3] = {real(0), real(0), real(0)};
 #pragma unroll
@@ -585,10 +607,15 @@ __global__ __launch_bounds__(TX* TY, OCC) void k_step_march(Coef<real> C, Fields
                         }
                     }
                     if constexpr (PSUM) {
-                        const int q = (tid / TX + 2) * SW + tid % TX + 2;
+                        const int q = (tid / TX + 1) * SW + tid % TX + 1;
 #pragma unroll
-                        for (int a = 0; a < Q; ++a) s_fs[a][q] = fs[a];
-                        acc[1] += bsum;
+                        for (int a = 0; a < Q; ++a)
+                            if (SLOT[a] >= 0) s_fs[SPAD + SLOT[a] * SS + q] = fs[a];
+                        // what stays in the column: the rest population and
+                        // +-z (slices cc, cc + 1, cc - 1), and the bounce-backs
+                        acc[1] += fs[0] + bsum;
+                        acc[2] += fs[5];
+                        acc[0] += fs[6];
                     }
                 }
             }
@@ -814,23 +841,26 @@ template <>
 struct Variants3D<float> {
     static constexpr int count = 14;
     static constexpr int preferred = 2;  // 32 x 8 cross-section, chunks of 8 slices
-    // on lattices its blocks tile: the 32 x 8 x 32 sweep that forms the next
-    // density (0.730 ms against 0.815 ms for a step on the 256^3 sphere)
-    static constexpr int preferred_psum = 12;
+    // on lattices their blocks tile, in this order: the sweeps that form the
+    // next density (32 x 8 x 16: 0.712 ms against 0.820 ms for the best
+    // plain sweep and its density pass, a step on the 256^3 sphere)
+    static constexpr int npsum = 2;
+    static constexpr int preferred_psum[npsum] = {11, 10};
     static constexpr Shape3D shape[count] = {
         {32, 8, 16, true, false, 1, false}, {32, 8, 16, false, false, 1, false},
         {32, 8, 8, true, false, 1, false},  {32, 8, 32, true, false, 1, false},
         {16, 16, 16, true, false, 1, false}, {32, 8, 16, true, true, 1, false},
         {32, 8, 32, true, true, 1, false},  {32, 8, 2, true, false, 1, true},
         {64, 4, 16, true, false, 1, false}, {256, 2, 16, true, false, 1, false},
-        {32, 8, 8, true, false, 1, false, true}, {32, 8, 16, true, false, 1, false, true},
-        {32, 8, 32, true, false, 1, false, true}, {32, 8, 8, true, false, 4, false, true}};
+        {32, 8, 8, true, false, 4, false, true}, {32, 8, 16, true, false, 4, false, true},
+        {32, 8, 32, true, false, 4, false, true}, {32, 8, 32, true, false, 1, false, true}};
 };
 template <>
 struct Variants3D<double> {
     static constexpr int count = 5;
     static constexpr int preferred = 3;  // the brick: 1.63 ms against 1.76 ms on the 256^3 sphere
-    static constexpr int preferred_psum = -1;
+    static constexpr int npsum = 0;
+    static constexpr int preferred_psum[1] = {-1};
     static constexpr Shape3D shape[count] = {
         {32, 8, 16, true, false, 1, false}, {32, 8, 16, false, false, 1, false},
         {32, 8, 16, true, true, 1, false}, {32, 8, 2, true, false, 1, true},
@@ -848,12 +878,12 @@ static bool psum_applies(const Coef<real>& C, const Shape3D& sh);
 // the variant a D3Q19 context starts with (fastest on the 256^3 benchmark)
 template <typename real>
 int step3d_preferred_variant(int nx, int ny, int nz) {
-    constexpr int v = Variants3D<real>::preferred_psum;
-    if constexpr (v >= 0) {
-        Coef<real> C{};
-        C.nx = nx;
-        C.ny = ny;
-        C.nz = nz;
+    Coef<real> C{};
+    C.nx = nx;
+    C.ny = ny;
+    C.nz = nz;
+    for (int k = 0; k < Variants3D<real>::npsum; ++k) {
+        const int v = Variants3D<real>::preferred_psum[k];
         if (psum_applies(C, Variants3D<real>::shape[v])) return v;
     }
     return Variants3D<real>::preferred;
