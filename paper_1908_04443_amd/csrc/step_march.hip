@@ -367,6 +367,26 @@ __global__ __launch_bounds__(TX* TY, OCC) void k_step_march(Coef<real> C, Fields
     real d_umax = real(0), d_rmin = real(1e30), d_rmax = real(-1e30);
     int d_cnt = 0;
 
+    // classes and densities of the next slice to enter the rings (not
+    // fused): loaded one iteration before phase A writes them to LDS, so
+    // the barrier after phase A does not wait for HBM
+    uint8_t pc_own = CLS_SOLID, pc_ring[JR];
+    real pr_own = real(0), pr_ring[JR];
+    auto issue_slice = [&](int it) __attribute__((always_inline)) {
+        const uint32_t base = (uint32_t)wrapi(c0 - 2 + it, nc) * nab;
+        pc_own = Fd.cls[base + own_ab];
+        pr_own = Fd.rho[base + own_ab];
+#pragma unroll
+        for (int jj = 0; jj < JR; ++jj) {
+            pc_ring[jj] = CLS_SOLID;
+            pr_ring[jj] = real(0);
+            if (tid + jj * NT < RING) {
+                pc_ring[jj] = Fd.cls[base + ring_ab[jj]];
+                pr_ring[jj] = Fd.rho[base + ring_ab[jj]];
+            }
+        }
+    };
+
     // Rl: populations of the owned node of slice c0 - 2 + it (fused only);
     // Rc: those of slice c0 - 4 + it, loaded two iterations earlier (fused)
     // or in phase A of this iteration
@@ -415,16 +435,18 @@ __global__ __launch_bounds__(TX* TY, OCC) void k_step_march(Coef<real> C, Fields
                         Rc[a] = io.ld(a, PULL ? up_node<L>(a, own_a, own_b, ccA, na, nb, nc, nab)
                                               : (uint32_t)ccA * nab + own_ab);
                 }
-                // densities come from the density pass: one value per node
-                s_cls[slot][own_p] = Fd.cls[base + own_ab];
-                s_rho[slot][own_p] = Fd.rho[base + own_ab];
+                // densities come from the density pass: one value per node,
+                // loaded in the previous iteration
+                s_cls[slot][own_p] = pc_own;
+                s_rho[slot][own_p] = pr_own;
 #pragma unroll
                 for (int jj = 0; jj < JR; ++jj) {
                     if (tid + jj * NT < RING) {
-                        s_cls[slot][ring_p[jj]] = Fd.cls[base + ring_ab[jj]];
-                        s_rho[slot][ring_p[jj]] = Fd.rho[base + ring_ab[jj]];
+                        s_cls[slot][ring_p[jj]] = pc_ring[jj];
+                        s_rho[slot][ring_p[jj]] = pr_ring[jj];
                     }
                 }
+                if (it + 1 < TZ + 4) issue_slice(it + 1);
             }
         }
         __syncthreads();
@@ -632,6 +654,7 @@ __global__ __launch_bounds__(TX* TY, OCC) void k_step_march(Coef<real> C, Fields
         }
     } else {
         real R0[Q];
+        issue_slice(0);
         for (int it = 0; it < TZ + 4; ++it) body(it, R0, R0);
     }
     if constexpr (PSUM) {
@@ -842,10 +865,10 @@ struct Variants3D<float> {
     static constexpr int count = 14;
     static constexpr int preferred = 2;  // 32 x 8 cross-section, chunks of 8 slices
     // on lattices their blocks tile, in this order: the sweeps that form the
-    // next density (32 x 8 x 16: 0.712 ms against 0.820 ms for the best
+    // next density (32 x 8 x 8: 0.662 ms against 0.805 ms for the best
     // plain sweep and its density pass, a step on the 256^3 sphere)
     static constexpr int npsum = 2;
-    static constexpr int preferred_psum[npsum] = {11, 10};
+    static constexpr int preferred_psum[npsum] = {10, 11};
     static constexpr Shape3D shape[count] = {
         {32, 8, 16, true, false, 1, false}, {32, 8, 16, false, false, 1, false},
         {32, 8, 8, true, false, 1, false},  {32, 8, 32, true, false, 1, false},

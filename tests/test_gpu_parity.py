@@ -231,7 +231,7 @@ def _nvariants(lattice, precision):
 
 
 @pytest.mark.parametrize("precision", [8, 4])
-@pytest.mark.parametrize("variant", range(16))
+@pytest.mark.parametrize("variant", range(24))
 def test_every_d2q9_variant(oracle_mod, gpu_lib, precision, variant):
     if variant >= _nvariants(9, precision):
         pytest.skip("no such variant")
