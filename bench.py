@@ -67,24 +67,24 @@ def setup_solver(L, W, params, data, n_wall_max):
     return s, len(walls)
 
 
-def time_steps(s, warmup, steps, segments=5):
-    """Warm up, then time exactly `steps` steps as `segments` consecutive
-    runs, each bracketed by HIP events on the solver's stream.  Returns the
-    wall-clock time of all of them (synchronised before and after) and the
-    median event time per step over the segments."""
+def time_steps(s, warmup, steps, runs=5):
+    """Warm up, then time exactly `steps` steps: one call with HIP events on
+    the solver's stream around its launches, bracketed by host
+    synchronisations for the wall clock.  After the timed region, `runs`
+    more event-timed runs of max(200, min(steps, 2000)) steps give the
+    median time per step.  Returns (wall seconds of the timed region, event
+    ms per step over it, median event ms per step of the runs, the runs)."""
     import numpy as np
     import torch
     s.step(warmup)
     torch.cuda.synchronize()
-    sizes = [steps // segments + (1 if i < steps % segments else 0) for i in range(segments)]
-    per_step = []
     t0 = time.perf_counter()
-    for n in sizes:
-        if n:
-            per_step.append(s.step_timed(n) / n)
+    ms = s.step_timed(steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    return wall, float(np.median(per_step)), [round(x, 5) for x in per_step]
+    n = max(200, min(steps, 2000))
+    per_run = [s.step_timed(n) / n for _ in range(runs)]
+    return wall, ms / steps, float(np.median(per_run)), [round(x, 5) for x in per_run]
 
 
 def run_c1(L, W, steps, warmup):
@@ -96,7 +96,7 @@ def run_c1(L, W, steps, warmup):
     s, nw = setup_solver(L, W, p, data, int(solid.sum()))
     rc, d0 = s.diagnostics()
     variant = s.variant
-    wall, ms_step, seg = time_steps(s, warmup, steps)
+    wall, ms_step, ms_med, runs = time_steps(s, warmup, steps)
     # diagnostics (field-mode pass over f, per-tile partials, fixed-order
     # final reduction, copy to the host and a stream synchronisation)
     s.diagnostics()
@@ -109,7 +109,7 @@ def run_c1(L, W, steps, warmup):
     N = 2048 * 2048
     nf = int((solid == 0).sum())
     s.close()
-    return dict(N=N, n_fluid=nf, n_wall=nw, wall=wall, ms_step=ms_step, segments=seg,
+    return dict(N=N, n_fluid=nf, n_wall=nw, wall=wall, ms_step=ms_step, ms_median=ms_med, runs=runs,
                 variant=variant, diag_ms=diag_ms,
                 mass_drift=abs(d1["mass"] - d0["mass"]) / d0["mass"], max_u=d1["max_u"],
                 rho=(d1["rho_min"], d1["rho_max"]), data=data, params=p)
@@ -121,14 +121,15 @@ def run_c2(L, W, steps, warmup):
     data = W.c2_sphere(p.rho_g, p.rho_l)
     solid = data["solid"]
     s, nw = setup_solver(L, W, p, data, int(solid.sum()))
-    wall, ms_step, seg = time_steps(s, warmup, steps)
+    wall, ms_step, ms_med, runs = time_steps(s, warmup, steps)
     rc, d1 = s.diagnostics()
     if rc != 0:
         raise RuntimeError("C2 run left the psi domain")
     N = 256 ** 3
     nf = int((solid == 0).sum())
     s.close()
-    return dict(N=N, n_fluid=nf, n_wall=nw, wall=wall, ms_step=ms_step, segments=seg, params=p)
+    return dict(N=N, n_fluid=nf, n_wall=nw, wall=wall, ms_step=ms_step, ms_median=ms_med, runs=runs,
+                params=p)
 
 
 def run_c3(L, W, steps, warmup, graph_steps=50):
@@ -380,7 +381,7 @@ def main():
     N, nf = c1["N"], c1["n_fluid"]
     ms_step = 1e3 * c1["wall"] / args.steps
     mlups = N * args.steps / c1["wall"] / 1e6
-    kern_s = c1["ms_step"] / 1e3  # HIP-event time per step, median of 5 segments
+    kern_s = c1["ms_step"] / 1e3  # HIP-event time per step over the timed region
     b_alg = 2 * 9 * 4 * nf  # one read + one write of every fluid population
     achieved = b_alg / kern_s / 1e9
     traffic = measured_traffic("k_step_d2q9", "c1")
@@ -410,7 +411,8 @@ def main():
                      "traffic": traffic,
                      "kernel": "k_step_d2q9", "bytes_per_launch_alg": b_alg,
                      "kernel_ms": round(kern_s * 1e3, 5),
-                     "kernel_ms_segments": c1["segments"]},
+                     "kernel_ms_median5": round(c1["ms_median"], 5),
+                     "kernel_ms_runs": c1["runs"]},
         "check": {"mass_rel_drift": c1["mass_drift"], "max_u": c1["max_u"],
                   "rho_min_max": c1["rho"]},
         # one read of every fluid population per diagnostics call
@@ -434,7 +436,8 @@ def main():
             "mlups": round(c2["N"] * args.c2_steps / c2["wall"] / 1e6, 2),
             "achieved_GBs": round(b2 / k2 / 1e9, 1),
             "frac": round(b2 / k2 / 1e9 / HBM_PEAK_GBS, 4),
-            "kernel_ms": round(k2 * 1e3, 5), "kernel_ms_segments": c2["segments"],
+            "kernel_ms": round(k2 * 1e3, 5), "kernel_ms_median5": round(c2["ms_median"], 5),
+            "kernel_ms_runs": c2["runs"],
             "steps": args.c2_steps,
             "traffic": measured_traffic("d3q19_step", "c2")}
         log(f"C2: {out['secondary']['d3q19_256cubed_fp32']}")

@@ -34,6 +34,17 @@ def test_header_symbols_exported(L):
     assert not missing, missing
 
 
+def test_header_constants_match_the_binding(L):
+    """Every numeric #define of the header has the same value in the
+    binding (shifts and plain integers)."""
+    txt = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    defs = re.findall(r"#define\s+(LBM_[A-Z0-9_]+)\s+\(?\s*(\d+)u?\s*(?:<<\s*(\d+))?\s*\)?", txt)
+    assert len(defs) >= 1
+    for name, base, shift in defs:
+        want = int(base) << int(shift or 0)
+        assert getattr(L, name) == want, name
+
+
 def test_status_strings(L):
     lib = L.lib()
     for code in (0, -1, -2, -3, -4, -5):
