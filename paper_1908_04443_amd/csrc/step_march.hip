@@ -127,73 +127,86 @@ struct PsumFaces {
 // and across the edges between two of those faces; D3Q19 has no velocity
 // along a body diagonal, so the block across a corner sends nothing.  The
 // six candidates are read unconditionally (a candidate that does not apply
-// reads the block's first value and adds 0), so the loads of a wave are in
+// reads the first value of the face array and adds 0), so the loads of a wave are in
 // flight together.  The offset of the neighbour (not its absolute position)
 // locates the node in the neighbour's part, so a block that is its own
 // periodic neighbour is handled too.
-template <typename real, int TX, int TY, int TZ>
+template <typename real, int TX, int TY, int TZ, int NPT>
 __global__ __launch_bounds__(256) void k_psum_close(const uint8_t* __restrict__ cls,
                                                     real* __restrict__ rho,
                                                     const real* __restrict__ ring, int na, int nb,
                                                     int nc) {
     static_assert(TX > 2 && TY > 2 && TZ > 2, "a block has interior nodes along every axis");
     using PF = PsumFaces<TX, TY, TZ>;
-    // one thread per face node: per block the two z faces (TX x TY), the
-    // two y faces without their z edges (TX x (TZ - 2)), then the two x
-    // faces without either (TY - 2) x (TZ - 2)
+    // NPT face nodes per thread, gridDim.x * 256 apart, all loads issued
+    // before any sum.  Per block of the sweep: the two z faces (TX x TY),
+    // the two y faces without their z edges (TX x (TZ - 2)), then the two x
+    // faces without either ((TY - 2) x (TZ - 2)).
     constexpr int ZF = TX * TY, YF = TX * (TZ - 2), XF = (TY - 2) * (TZ - 2);
     constexpr uint32_t FPB = 2 * ZF + 2 * YF + 2 * XF;
     const int gx = na / TX, gy = nb / TY, gz = nc / TZ;
-    const uint32_t t = blockIdx.x * 256u + threadIdx.x;
-    if (t >= (uint32_t)gx * (uint32_t)gy * (uint32_t)gz * FPB) return;
-    const uint32_t b = t / FPB;
-    int q = (int)(t - b * FPB), i, j, k;
-    if (q < 2 * ZF) {
-        k = q < ZF ? 0 : TZ - 1;
-        q = q < ZF ? q : q - ZF;
-        i = q % TX;
-        j = q / TX;
-    } else if ((q -= 2 * ZF) < 2 * YF) {
-        j = q < YF ? 0 : TY - 1;
-        q = q < YF ? q : q - YF;
-        i = q % TX;
-        k = 1 + q / TX;
-    } else {
-        q -= 2 * YF;
-        i = q < XF ? 0 : TX - 1;
-        q = q < XF ? q : q - XF;
-        j = 1 + q % (TY - 2);
-        k = 1 + q / (TY - 2);
-    }
-    const int bx = (int)(b % (uint32_t)gx), by = (int)((b / (uint32_t)gx) % (uint32_t)gy);
-    const int bz = (int)(b / ((uint32_t)gx * (uint32_t)gy));
-    const int fx = i == 0 ? -1 : (i == TX - 1 ? 1 : 0);
-    const int fy = j == 0 ? -1 : (j == TY - 1 ? 1 : 0);
-    const int fz = k == 0 ? -1 : (k == TZ - 1 ? 1 : 0);
-    const uint32_t n = ((uint32_t)(bz * TZ + k) * (uint32_t)nb + (uint32_t)(by * TY + j)) *
-                           (uint32_t)na + (uint32_t)(bx * TX + i);
+    const uint32_t total = (uint32_t)gx * (uint32_t)gy * (uint32_t)gz * FPB;
     auto wrap1 = [](int v, int m) { return v < 0 ? v + m : (v >= m ? v - m : v); };
-    const int ox[6] = {fx, 0, 0, fx, fx, 0};
-    const int oy[6] = {0, fy, 0, fy, 0, fy};
-    const int oz[6] = {0, 0, fz, 0, fz, fz};
-    real v[6];
+    real v[NPT][6], r[NPT];
+    uint8_t cl[NPT];
+    uint32_t nn[NPT];
+    bool ok[NPT];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
-        const bool use = (c < 3) ? ((ox[c] | oy[c] | oz[c]) != 0)
-                                 : (c == 3 ? (fx != 0 && fy != 0)
-                                           : (c == 4 ? (fx != 0 && fz != 0) : (fy != 0 && fz != 0)));
-        const int nbx = wrap1(bx + ox[c], gx), nby = wrap1(by + oy[c], gy),
-                  nbz = wrap1(bz + oz[c], gz);
-        const size_t at = (size_t)(nbx + gx * (nby + gy * nbz)) * PF::size +
-                          PF::index(i - ox[c] * TX, j - oy[c] * TY, k - oz[c] * TZ);
-        v[c] = ring[use ? at : (size_t)0];
-        v[c] = use ? v[c] : real(0);
+    for (int p = 0; p < NPT; ++p) {
+        const uint32_t t0 = (blockIdx.x + (uint32_t)p * gridDim.x) * 256u + threadIdx.x;
+        ok[p] = t0 < total;
+        const uint32_t t = ok[p] ? t0 : 0u;  // a thread past the end reads node 0 and stores nothing
+        const uint32_t b = t / FPB;
+        int q = (int)(t - b * FPB), i, j, k;
+        if (q < 2 * ZF) {
+            k = q < ZF ? 0 : TZ - 1;
+            q = q < ZF ? q : q - ZF;
+            i = q % TX;
+            j = q / TX;
+        } else if ((q -= 2 * ZF) < 2 * YF) {
+            j = q < YF ? 0 : TY - 1;
+            q = q < YF ? q : q - YF;
+            i = q % TX;
+            k = 1 + q / TX;
+        } else {
+            q -= 2 * YF;
+            i = q < XF ? 0 : TX - 1;
+            q = q < XF ? q : q - XF;
+            j = 1 + q % (TY - 2);
+            k = 1 + q / (TY - 2);
+        }
+        const int bx = (int)(b % (uint32_t)gx), by = (int)((b / (uint32_t)gx) % (uint32_t)gy);
+        const int bz = (int)(b / ((uint32_t)gx * (uint32_t)gy));
+        const int fx = i == 0 ? -1 : (i == TX - 1 ? 1 : 0);
+        const int fy = j == 0 ? -1 : (j == TY - 1 ? 1 : 0);
+        const int fz = k == 0 ? -1 : (k == TZ - 1 ? 1 : 0);
+        nn[p] = ((uint32_t)(bz * TZ + k) * (uint32_t)nb + (uint32_t)(by * TY + j)) * (uint32_t)na +
+                (uint32_t)(bx * TX + i);
+        const int ox[6] = {fx, 0, 0, fx, fx, 0};
+        const int oy[6] = {0, fy, 0, fy, 0, fy};
+        const int oz[6] = {0, 0, fz, 0, fz, fz};
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            const bool use = (c < 3) ? ((ox[c] | oy[c] | oz[c]) != 0)
+                                     : (c == 3 ? (fx != 0 && fy != 0)
+                                               : (c == 4 ? (fx != 0 && fz != 0) : (fy != 0 && fz != 0)));
+            const int nbx = wrap1(bx + ox[c], gx), nby = wrap1(by + oy[c], gy),
+                      nbz = wrap1(bz + oz[c], gz);
+            const size_t at = (size_t)(nbx + gx * (nby + gy * nbz)) * PF::size +
+                              PF::index(i - ox[c] * TX, j - oy[c] * TY, k - oz[c] * TZ);
+            v[p][c] = ring[use ? at : (size_t)0];
+            v[p][c] = use ? v[p][c] : real(0);
+        }
+        cl[p] = cls[nn[p]];
+        r[p] = rho[nn[p]];
     }
-    const uint8_t cl = cls[n];
-    real r = rho[n];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) r += v[c];
-    if (cl == CLS_FLUID) rho[n] = r;
+    for (int p = 0; p < NPT; ++p) {
+        real s = r[p];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) s += v[p][c];
+        if (ok[p] && cl[p] == CLS_FLUID) rho[nn[p]] = s;
+    }
 }
 
 // FUSED: no density pass.  Phase A loads the populations of its slice,
@@ -944,9 +957,10 @@ static void launch_v3(const Coef<real>& C, const Fields<real>& F, const FieldOut
                                      2 * (sh.TY - 2) * (sh.TZ - 2);
             const uint32_t faces = (uint32_t)(C.nx / sh.TX) * (uint32_t)(C.ny / sh.TY) *
                                    (uint32_t)(C.nz / sh.TZ) * fpb;
-            hipLaunchKernelGGL((k_psum_close<real, sh.TX, sh.TY, sh.TZ>),
-                               dim3((faces + 255) / 256), dim3(256), 0, s, F.cls, F.rho_next,
-                               F.ring, C.nx, C.ny, C.nz);
+            constexpr int NPT = 2;  // face nodes per thread
+            hipLaunchKernelGGL((k_psum_close<real, sh.TX, sh.TY, sh.TZ, NPT>),
+                               dim3((faces + 256 * NPT - 1) / (256 * NPT)), dim3(256), 0, s, F.cls,
+                               F.rho_next, F.ring, C.nx, C.ny, C.nz);
         } else {
             hipLaunchKernelGGL((k_step_march<D3Q19, real, sh.TX, sh.TY, sh.TZ, MODE_STEP, sh.xcd,
                                              true, false, sh.occ>),
