@@ -617,6 +617,7 @@ __global__ __launch_bounds__(TX* TY, OCC) void k_step_march(Coef<real> C, Fields
                     collide<L, real>(C, fl, rho, F, Fm, psi_c, fs, u);
                     const int ga = own_a, gb = D3 ? own_b : 0;
                     real bsum = real(0);  // PSUM: bounce-backs return to this node
+                    uint32_t wmask = 0;   // pull form: directions whose neighbour is not fluid
 #pragma unroll
                     for (int a = 0; a < Q; ++a) {
                         const int ea = L::ex[a];
@@ -625,20 +626,37 @@ __global__ __launch_bounds__(TX* TY, OCC) void k_step_march(Coef<real> C, Fields
                         const int s3 = (it - 2 + ec + NSLOT) % NSLOT;
                         const int q = own_p + ea + eb * PA;
                         const bool fluid_to = s_cls[s3][q] == CLS_FLUID;
-                        int ta = ga + ea, tb = gb + eb, tc = cc + ec;
-                        ta = ta < 0 ? ta + na : (ta >= na ? ta - na : ta);
-                        tb = tb < 0 ? tb + nb : (tb >= nb ? tb - nb : tb);
-                        tc = tc < 0 ? tc + nc : (tc >= nc ? tc - nc : tc);
-                        const uint32_t t = (uint32_t)tc * nab + (uint32_t)tb * na + ta;
                         if constexpr (PULL) {
-                            // own slot; a wall neighbour also gets the bounce-back
+                            // own slot; the bounce-backs follow, in one branch
+                            // that waves away from walls skip
                             io.st_nt(a, n, fs[a]);
-                            if (!fluid_to) io.st(L::opp[a], t, fs[a]);
-                            if (PSUM && !fluid_to) bsum += fs[a];
-                        } else if (fluid_to) {
-                            io.st(a, t, fs[a]);
+                            wmask |= fluid_to ? 0u : (1u << a);
+                            if (PSUM) bsum += fluid_to ? real(0) : fs[a];
                         } else {
-                            io.st(L::opp[a], n, fs[a]);
+                            int ta = ga + ea, tb = gb + eb, tc = cc + ec;
+                            ta = ta < 0 ? ta + na : (ta >= na ? ta - na : ta);
+                            tb = tb < 0 ? tb + nb : (tb >= nb ? tb - nb : tb);
+                            tc = tc < 0 ? tc + nc : (tc >= nc ? tc - nc : tc);
+                            const uint32_t t = (uint32_t)tc * nab + (uint32_t)tb * na + ta;
+                            if (fluid_to) io.st(a, t, fs[a]);
+                            else io.st(L::opp[a], n, fs[a]);
+                        }
+                    }
+                    if constexpr (PULL) {
+                        if (wmask != 0u) {
+                            // a wall neighbour's slot opp(a) gets f*_a, where the
+                            // gather of direction opp(a) at this node looks
+#pragma unroll
+                            for (int a = 1; a < Q; ++a) {
+                                if ((wmask >> a) & 1u) {
+                                    int ta = ga + L::ex[a], tb = gb + L::ey[a], tc = cc + L::ez[a];
+                                    ta = ta < 0 ? ta + na : (ta >= na ? ta - na : ta);
+                                    tb = tb < 0 ? tb + nb : (tb >= nb ? tb - nb : tb);
+                                    tc = tc < 0 ? tc + nc : (tc >= nc ? tc - nc : tc);
+                                    io.st(L::opp[a], (uint32_t)tc * nab + (uint32_t)tb * na + ta,
+                                          fs[a]);
+                                }
+                            }
                         }
                     }
                     if constexpr (PSUM) {
