@@ -30,7 +30,7 @@ class Params(C.Structure):
         ("sigma", C.c_double), ("body_force", C.c_double * 3),
         ("scheme", C.c_int32), ("rho_w", C.c_double), ("G_w", C.c_double),
         ("rho_g", C.c_double), ("rho_l", C.c_double), ("sfi_solid_psi", C.c_int32),
-        ("sfi_psi_presum", C.c_int32),
+        ("sfi_psi_presum", C.c_int32), ("sfi_lattice_weights", C.c_int32),
     ]
 
 
@@ -92,7 +92,8 @@ def _check(rc, what):
 def make_params(lattice=9, nx=16, ny=16, nz=1, tau=1.0, eos=EOS_CS, a=1.0, b=4.0,
                 R=1.0, T=None, T_ratio=0.75, omega=0.344, G=-1.0, sigma=0.0,
                 body_force=(0.0, 0.0, 0.0), scheme=IVD, rho_w=0.0, G_w=0.0,
-                rho_g=None, rho_l=None, sfi_solid_psi=0, sfi_psi_presum=0):
+                rho_g=None, rho_l=None, sfi_solid_psi=0, sfi_psi_presum=0,
+                sfi_lattice_weights=0):
     """Build a Params struct; T defaults to T_ratio * Tc and the limiter
     bounds to the Maxwell coexistence densities, both from the oracle."""
     p = Params()
@@ -111,6 +112,7 @@ def make_params(lattice=9, nx=16, ny=16, nz=1, tau=1.0, eos=EOS_CS, a=1.0, b=4.0
         p.body_force[i] = body_force[i]
     p.scheme, p.rho_w, p.G_w = scheme, rho_w, G_w
     p.sfi_solid_psi, p.sfi_psi_presum = sfi_solid_psi, sfi_psi_presum
+    p.sfi_lattice_weights = sfi_lattice_weights
     if rho_g is None or rho_l is None:
         g, l = coexistence(p)
         rho_g = g if rho_g is None else rho_g

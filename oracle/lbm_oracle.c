@@ -167,6 +167,7 @@ static int check_params(const orc_params* p) {
     if (p->scheme == ORC_GF && p->lattice != 9) return ORC_EINVAL;  /* 2-D scheme */
     if (p->sfi_solid_psi < 0 || p->sfi_solid_psi > 4) return ORC_EINVAL;
     if (p->sfi_psi_presum != 0 && p->sfi_psi_presum != 1) return ORC_EINVAL;
+    if (p->sfi_lattice_weights != 0 && p->sfi_lattice_weights != 1) return ORC_EINVAL;
     return ORC_OK;
 }
 
@@ -606,7 +607,8 @@ static int macro_phases(const orc_params* p, const lat_t* L, const geom_t* g,
             real psy = (own && solid[y]) ? w->psi[n] : w->psi[y];
             for (int d = 0; d < D; ++d) {
                 sm[d] += L->w[a] * psy * (double)L->e[3 * a + d];
-                if (solid[y]) sa[d] += L->w[a] * (double)L->e[3 * a + d];
+                if (solid[y])
+                    sa[d] += (p->sfi_lattice_weights ? L->t[a] : L->w[a]) * (double)L->e[3 * a + d];
             }
         }
         for (int d = 0; d < D; ++d) {

@@ -54,6 +54,9 @@ typedef struct {
     /* SFI only: pre-sum factor of Eq. 8; 0: rho(x) as printed, 1: psi(x)
      * (for the same study) */
     int32_t sfi_psi_presum;
+    /* SFI only: weights of the sum in Eq. 8; 0: those of Eq. 5 (1/3, 1/12 in
+     * D2Q9), 1: the lattice weights (1/9, 1/36) (for the same study) */
+    int32_t sfi_lattice_weights;
 } orc_params;
 
 /* ---- thermodynamics (real arithmetic) ---- */

@@ -15,7 +15,9 @@ sfi_readings.json:
   own    each fluid node sees its solid neighbours at its own psi
 
 each with the pre-sum factor of Eq. 8 as printed, rho(x), and with psi(x)
-(the variant of Raiskinmaki et al. that the introduction mentions).
+(the variant of Raiskinmaki et al. that the introduction mentions), and
+with the weights of the sum in Eq. 8 taken as those of Eq. 5 (1/3, 1/12)
+or, with --weights lattice, as the lattice weights (1/9, 1/36).
 
 Runs at half the paper's scale by default (150 x 175, R = 35, droplet
 r = 25, 12000 steps); --full runs 300 x 350, R = 70, r = 50, 40000 steps.
@@ -43,7 +45,7 @@ GW = (-0.6, 0.3, 1.2)
 PRINTED = {-0.6: 38.0, 0.3: 59.0, 1.2: 119.0}
 
 
-def run(reading, presum, G_w, scale, steps, sigma):
+def run(reading, presum, G_w, scale, steps, sigma, lattice_weights=0):
     nx, ny = 300 // scale, 350 // scale
     R, r0 = 70 // scale, 50 // scale
     cc, dc = (nx // 2, 130 // scale), (nx // 2, 230 // scale)
@@ -51,11 +53,13 @@ def run(reading, presum, G_w, scale, steps, sigma):
     tau[7] = tau[8] = 0.95  # nu = 0.15 (Sec. IV A)
     p = O.make_params(nx=nx, ny=ny, eos=O.EOS_PR, a=2.0 / 49.0, b=2.0 / 21.0, T_ratio=0.86,
                       sigma=sigma, tau=tau, scheme=O.SFI, G_w=G_w,
-                      sfi_solid_psi=READINGS[reading], sfi_psi_presum=int(presum == "psi"))
+                      sfi_solid_psi=READINGS[reading], sfi_psi_presum=int(presum == "psi"),
+                      sfi_lattice_weights=lattice_weights)
     solid = I.disk_mask((ny, nx), cc, R)
     rho0 = I.droplet_rho((ny, nx), dc, r0, p.rho_g, p.rho_l, solid=solid)
     f = O.init_eq(p, solid, rho0)
-    out = dict(reading=reading, presum=presum, G_w=G_w, printed=PRINTED[G_w], nx=nx, ny=ny, steps=steps)
+    out = dict(reading=reading, presum=presum, weights="lattice" if lattice_weights else "eq5",
+               G_w=G_w, printed=PRINTED[G_w], nx=nx, ny=ny, steps=steps)
     try:
         f = O.run(p, solid, f, steps)
     except O.OracleError:
@@ -85,6 +89,7 @@ def main():
     ap.add_argument("--full", action="store_true")
     ap.add_argument("--readings", default=",".join(READINGS))
     ap.add_argument("--presum", default="rho,psi")
+    ap.add_argument("--weights", default="eq5", choices=("eq5", "lattice"))
     ap.add_argument("--out", default=os.path.join(HERE, "sfi_readings.json"))
     args = ap.parse_args()
     sigma = json.load(open(os.path.join(HERE, "sigma_calibration.json")))["pr_0.86"]["sigma"]
@@ -94,7 +99,7 @@ def main():
         for rd in args.readings.split(","):
             for gw in GW:
                 t0 = time.time()
-                r = run(rd, pre, gw, scale, steps, sigma)
+                r = run(rd, pre, gw, scale, steps, sigma, int(args.weights == "lattice"))
                 r["seconds"] = round(time.time() - t0, 1)
                 print(json.dumps(r), flush=True)
                 rows.append(r)

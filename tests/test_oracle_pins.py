@@ -171,20 +171,21 @@ def test_mass_conserved_with_walls(oracle_mod, scheme):
 
 
 @pytest.mark.parametrize("reading", [1, 2, 3, 4])
-@pytest.mark.parametrize("presum", [0, 1])
-def test_sfi_alternative_readings_flat_wall(oracle_mod, reading, presum):
+@pytest.mark.parametrize("presum,lattice_weights", [(0, 0), (1, 0), (0, 1)])
+def test_sfi_alternative_readings_flat_wall(oracle_mod, reading, presum, lattice_weights):
     """The alternative readings of the solid-fluid interaction scheme (what
     psi the solid nodes carry in Eq. 5; rho or psi in front of the sum of
-    Eq. 8), on a uniform fluid between two solid rows whose solid psi equals
-    the fluid's (mean of the fluid neighbours, own psi: any density; gas or
-    liquid psi: that density): the cohesive force vanishes, and next to a
-    flat wall the adhesion of Eq. 8 is -G_w X (w(1) + 2 w(2)) (0, -1) =
-    (0, G_w X / 2) below and its mirror image above, X = rho or psi.  Mass is
-    conserved over 50 steps."""
+    Eq. 8; the weights of its sum), on a uniform fluid between two solid rows
+    whose solid psi equals the fluid's (mean of the fluid neighbours, own
+    psi: any density; gas or liquid psi: that density): the cohesive force
+    vanishes, and next to a flat wall the adhesion of Eq. 8 is -G_w X (w(1) +
+    2 w(2)) (0, -1) = (0, G_w X / 2) below and its mirror image above, X =
+    rho or psi; with the lattice weights (1/9 + 2/36) it is (0, G_w X / 6).
+    Mass is conserved over 50 steps."""
     O = oracle_mod
     nx, ny, G_w = 8, 12, 0.05
     op = O.make_params(nx=nx, ny=ny, scheme=O.SFI, G_w=G_w, sfi_solid_psi=reading,
-                       sfi_psi_presum=presum)
+                       sfi_psi_presum=presum, sfi_lattice_weights=lattice_weights)
     rho_f = {1: 0.5 * (op.rho_g + op.rho_l), 2: op.rho_g, 3: op.rho_l, 4: op.rho_l}[reading]
     solid = np.zeros((ny, nx), np.uint8)
     solid[0] = solid[ny - 1] = 1
@@ -194,8 +195,9 @@ def test_sfi_alternative_readings_flat_wall(oracle_mod, reading, presum):
     Fx, Fy = F[0].reshape(ny, nx), F[1].reshape(ny, nx)
     X = np.sqrt(O.psi_arg(op, rho_f)) if presum else rho_f
     want = np.zeros((ny, nx))
-    want[1] = G_w * X / 2
-    want[ny - 2] = -G_w * X / 2
+    k = 6.0 if lattice_weights else 2.0
+    want[1] = G_w * X / k
+    want[ny - 2] = -G_w * X / k
     assert np.abs(Fx).max() < 1e-14
     assert np.abs(Fy - want).max() < 1e-14 * max(1.0, X)
     f = O.run(op, solid, f0, 50)
