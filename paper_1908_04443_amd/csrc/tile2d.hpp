@@ -228,7 +228,6 @@ __device__ __forceinline__ void d2q9_prologue(const Coef<real>& C, const Fields<
                                               const int ny, const int x0, const int y0,
                                               const int list_tile, TileLDS<real, TX, TY>& S,
                                               real (&f)[TY / (NT / TX)][9], bool& bad) {
-    using L = D2Q9;
     constexpr int LX = TX + 4, LY = TY + 4;
     constexpr int ROWS = NT / TX;
     constexpr int RPT = TY / ROWS;
