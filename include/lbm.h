@@ -253,7 +253,9 @@ int lbm_get_diagnostics(lbm_ctx* ctx, lbm_diag* host_out);
 
 /* lbm_step followed by a host wait, timed with HIP events recorded on the
  * context stream right before the first and after the last step launch;
- * ms_total receives the elapsed time of the nsteps launches. */
+ * ms_total receives the elapsed time of the nsteps launches.  The events
+ * carry no system-scope fence: read results through the library's calls or
+ * stream-ordered copies, as after lbm_step. */
 int lbm_step_timed(lbm_ctx* ctx, int64_t nsteps, double* ms_total);
 
 /* ------------------------------------------------------------ tuning */

@@ -838,6 +838,14 @@ size_t lbm_workspace_bytes(const lbm_params* p, int64_t n_wall_max) {
     return layout(*p, n_wall_max, nullptr);
 }
 
+// The timing events of a context: they only measure time, so they are
+// recorded without a system-scope fence (no cache writeback and
+// invalidation around the timed launches)
+static bool create_timing_events(lbm_ctx* c) {
+    return hipEventCreateWithFlags(&c->ev0, hipEventDisableSystemFence) == hipSuccess &&
+           hipEventCreateWithFlags(&c->ev1, hipEventDisableSystemFence) == hipSuccess;
+}
+
 int lbm_create(const lbm_params* p, void* stream, void* workspace, size_t ws_bytes,
                int64_t n_wall_max, lbm_ctx** out) {
     if (!out) return fail(LBM_EINVAL, "out is NULL");
@@ -867,7 +875,7 @@ int lbm_create(const lbm_params* p, void* stream, void* workspace, size_t ws_byt
     else
         c->variant = p->precision == 4 ? step3d_preferred_variant<float>(p->nx, p->ny, p->nz)
                                        : step3d_preferred_variant<double>(p->nx, p->ny, p->nz);
-    if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+    if (!create_timing_events(c)) {
         lbm_destroy(c);  // releases whichever event was created
         return fail(LBM_EDEVICE, "hipEventCreate failed");
     }
@@ -1318,7 +1326,7 @@ int lbm_create_batch(const lbm_params* p, int32_t ncases, const int32_t* nx, con
     c->ws_bytes = ws_bytes;
     c->is_batch = true;
     layout_batch(*p, ncases, nx, ny, n_wall_max, c);
-    if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+    if (!create_timing_events(c)) {
         lbm_destroy(c);  // releases whichever event was created
         return fail(LBM_EDEVICE, "hipEventCreate failed");
     }
