@@ -270,10 +270,11 @@ int lbm_get_variant(lbm_ctx* ctx, int32_t* variant);
 
 /* Autotuner: times `steps` steps of every variant on the current problem
  * (HIP events on the context stream, after 2 warm-up steps each) and keeps
- * the fastest.  save_dev: device buffer of Q*N reals used to save and
- * restore the state, so that tuning leaves the fields unchanged (scratch:
- * it holds the context's internal form, pull form for D3Q19); with NULL
- * the state advances by nvariants*(steps+2) steps.  ms_per_variant (host,
+ * the fastest.  save_dev: device buffer of lbm_autotune_save_bytes(ctx)
+ * bytes used to save and restore the state, so that tuning leaves the
+ * fields unchanged (scratch: it holds the context's internal form, pull
+ * form for D3Q19, rows padded to whole cache lines in a multi-case
+ * context); with NULL the state advances by nvariants*(steps+2) steps.  ms_per_variant (host,
  * nullable, lbm_variant_count entries) receives the mean step time of each.
  * If the environment variable LBM_AUTOTUNE_CACHE names a file, a cached
  * choice for the same lattice, precision and size (for a multi-case
@@ -282,6 +283,10 @@ int lbm_get_variant(lbm_ctx* ctx, int32_t* variant);
  * new results are appended as one line each. */
 int lbm_autotune(lbm_ctx* ctx, int64_t steps, void* save_dev, int32_t* best_out,
                  double* ms_per_variant);
+/* Size in bytes of lbm_autotune's save buffer for this context: Q * N
+ * reals for a single lattice, the whole population arena of a multi-case
+ * context; 0 for a NULL context. */
+size_t lbm_autotune_save_bytes(lbm_ctx* ctx);
 
 /* ------------------------------------------------------ graph replay */
 /* Replay `steps` steps (rounded up to even) as one HIP graph: lbm_step(n)

@@ -55,7 +55,7 @@ __global__ __launch_bounds__(NT) void k_adj_collide_d2q9(Coef<real> C, Fields<re
     const PopIO<real, BUF> lio(A.lam_in, A.lam_out, N, 9);
     bool bad = false;
     real f[RPT][9];
-    d2q9_prologue<real, TX, TY, NT, BUF>(C, Fd, io, nx, ny, x0, y0, 0, S, f, bad);
+    d2q9_prologue<real, TX, TY, NT, BUF>(C, Fd, io, nx, nx, ny, x0, y0, 0, S, f, bad);
 
     // ext of lam(t+1) on the tile + 1 halo (pulled by the streaming transpose)
     for (int i = tid; i < (TX + 2) * (TY + 2); i += NT) {

@@ -458,6 +458,7 @@ static Coef<real> case_coef(const lbm_ctx* c, const lbm_case& k) {
     C.nx = k.nx;
     C.ny = k.ny;
     C.nz = 1;
+    C.pitch = k.pitch;
     return C;
 }
 
@@ -566,6 +567,14 @@ static size_t state_bytes(const lbm_ctx* c) {
 // ---- multi-case layout: packed arenas for all cases
 static uint64_t round_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
 
+// Row pitch of a case's arrays: the width rounded up to whole 128-byte lines,
+// so that every row starts on a line (the arenas and each case's part start
+// on one too).  A row that does not start on a line splits each tile row of
+// the step into one more line at each end, partly written.
+static uint64_t case_pitch(int nx, size_t elem_bytes) {
+    return round_up((uint64_t)nx, 128 / elem_bytes);
+}
+
 static size_t layout_batch(const lbm_params& p, int ncases, const int32_t* nx, const int32_t* ny,
                            const int64_t* nwm, lbm_ctx* c) {
     Carver cv(c ? c->ws : nullptr, c ? c->ws_bytes : 0);
@@ -578,11 +587,13 @@ static size_t layout_batch(const lbm_params& p, int ncases, const int32_t* nx, c
         k.nx = nx[i];
         k.ny = ny[i];
         k.N = (int64_t)nx[i] * ny[i];
+        k.pitch = (int)case_pitch(nx[i], s);
+        k.NP = (int64_t)k.pitch * ny[i];
         k.n_wall_max = nwm[i];
         k.f_off = f_off;
-        f_off += round_up(9 * (uint64_t)k.N, 64);
+        f_off += round_up(9 * (uint64_t)k.NP, 64);
         k.node_off = node_off;
-        node_off += round_up((uint64_t)k.N, 256);
+        node_off += round_up((uint64_t)k.NP, 256);
         k.wall_off = wall_off;
         wall_off += round_up((uint64_t)(nwm[i] > 0 ? nwm[i] : 1), 64);
         const int parts = p.precision == 4 ? grid2d_blocks<float>(k.nx, k.ny, 0)
@@ -657,7 +668,8 @@ static int check_batch_args(const lbm_params* p, int32_t ncases, const int32_t* 
     if (rc != LBM_OK) return rc;
     for (int i = 0; i < ncases; ++i) {
         if (nx[i] < 1 || ny[i] < 1 || nwm[i] < 0) return fail(LBM_EINVAL, "bad case size");
-        if ((uint64_t)9 * nx[i] * ny[i] * p->precision > 0xFFFFFFFFull)
+        if ((uint64_t)9 * case_pitch(nx[i], (size_t)p->precision) * ny[i] * p->precision >
+            0xFFFFFFFFull)
             return fail(LBM_EINVAL, "a case's populations must stay below 4 GiB");
     }
     return LBM_OK;
@@ -668,7 +680,7 @@ static int upload_cases(lbm_ctx* c) {
     std::vector<CaseDesc> d(c->cases.size());
     for (size_t i = 0; i < d.size(); ++i) {
         const lbm_case& k = c->cases[i];
-        d[i] = CaseDesc{k.nx, k.ny, k.f_off, k.node_off, k.wall_off};
+        d[i] = CaseDesc{k.nx, k.ny, k.pitch, 0, k.f_off, k.node_off, k.wall_off};
     }
     LBM_HIP(hipMemcpyAsync(c->d_cases, d.data(), d.size() * sizeof(CaseDesc),
                            hipMemcpyHostToDevice, c->stream));
@@ -1297,6 +1309,8 @@ int lbm_autotune(lbm_ctx* c, int64_t steps, void* save_dev, int32_t* best_out,
     return LBM_OK;
 }
 
+size_t lbm_autotune_save_bytes(lbm_ctx* c) { return c ? state_bytes(c) : 0; }
+
 size_t lbm_batch_workspace_bytes(const lbm_params* p, int32_t ncases, const int32_t* nx,
                                  const int32_t* ny, const int64_t* n_wall_max) {
     if (check_batch_args(p, ncases, nx, ny, n_wall_max) != LBM_OK) return 0;
@@ -1367,10 +1381,14 @@ int lbm_set_geometry_case(lbm_ctx* c, int32_t i, const uint8_t* solid_host) {
     if ((int64_t)g.walls.size() > k->n_wall_max)
         return fail(LBM_EINVAL, "case geometry has more wall nodes than its n_wall_max");
     if (g.n_fluid == 0) return fail(LBM_EINVAL, "case geometry has no fluid node");
-    LBM_HIP(hipMemcpyAsync(c->cls + k->node_off, g.cls.data(), (size_t)k->N,
-                           hipMemcpyHostToDevice, c->stream));
-    LBM_HIP(hipMemcpyAsync(c->widx + k->node_off, g.widx.data(), (size_t)k->N * 4,
-                           hipMemcpyHostToDevice, c->stream));
+    // rows `pitch` apart; the columns past nx are solid with no wall entry
+    LBM_HIP(hipMemsetAsync(c->cls + k->node_off, CLS_SOLID, (size_t)k->NP, c->stream));
+    LBM_HIP(hipMemsetAsync(c->widx + k->node_off, 0xFF, (size_t)k->NP * 4, c->stream));
+    LBM_HIP(hipMemcpy2DAsync(c->cls + k->node_off, (size_t)k->pitch, g.cls.data(), (size_t)k->nx,
+                             (size_t)k->nx, (size_t)k->ny, hipMemcpyHostToDevice, c->stream));
+    LBM_HIP(hipMemcpy2DAsync(c->widx + k->node_off, (size_t)k->pitch * 4, g.widx.data(),
+                             (size_t)k->nx * 4, (size_t)k->nx * 4, (size_t)k->ny,
+                             hipMemcpyHostToDevice, c->stream));
     LBM_HIP(hipStreamSynchronize(c->stream));
     const int64_t nw = (int64_t)g.walls.size();
     if (c->prec == 4) {
@@ -1427,16 +1445,16 @@ int lbm_set_fields_case(lbm_ctx* c, int32_t i, const void* rho_dev, const void* 
     if (rc != LBM_OK) return rc;
     if (!rho_dev) return fail(LBM_EINVAL, "NULL rho");
     if (!k->have_geom) return fail(LBM_ESTATE, "set the case geometry before its fields");
-    const int64_t QN = 9 * k->N;
+    const int64_t QN = 9 * k->NP;
     if (c->prec == 4) {
         LBM_HIP(launch_init_eq<float>(9, c->cls + k->node_off, (const float*)rho_dev,
-                                      (const float*)u_dev, (float*)c->f[c->cur] + k->f_off, k->N,
-                                      c->stream));
+                                      (const float*)u_dev, (float*)c->f[c->cur] + k->f_off, k->NP,
+                                      c->stream, k->nx, k->pitch));
         LBM_HIP(launch_fill<float>((float*)c->f[c->cur ^ 1] + k->f_off, 0.f, QN, c->stream));
     } else {
         LBM_HIP(launch_init_eq<double>(9, c->cls + k->node_off, (const double*)rho_dev,
                                        (const double*)u_dev, (double*)c->f[c->cur] + k->f_off,
-                                       k->N, c->stream));
+                                       k->NP, c->stream, k->nx, k->pitch));
         LBM_HIP(launch_fill<double>((double*)c->f[c->cur ^ 1] + k->f_off, 0.0, QN, c->stream));
     }
     LBM_HIP(launch_fill_i32(c->flag, 0, 4, c->stream));
@@ -1455,9 +1473,11 @@ int lbm_get_fields_case(lbm_ctx* c, int32_t i, void* rho_dev, void* u_dev, void*
                           : case_fields_launch<double>(c, *k, (double*)rho_dev, (double*)u_dev, nullptr);
         if (rc != LBM_OK) return rc;
     }
-    if (f_dev)
-        LBM_HIP(hipMemcpyAsync(f_dev, (char*)c->f[c->cur] + k->f_off * c->prec,
-                               (size_t)9 * k->N * c->prec, hipMemcpyDeviceToDevice, c->stream));
+    if (f_dev)  // the 9 planes' rows, dense
+        LBM_HIP(hipMemcpy2DAsync(f_dev, (size_t)k->nx * c->prec,
+                                 (char*)c->f[c->cur] + k->f_off * c->prec,
+                                 (size_t)k->pitch * c->prec, (size_t)k->nx * c->prec,
+                                 (size_t)9 * k->ny, hipMemcpyDeviceToDevice, c->stream));
     return LBM_OK;
 }
 

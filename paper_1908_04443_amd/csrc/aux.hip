@@ -6,16 +6,21 @@ namespace lbm {
 
 template <typename L, typename real>
 __global__ void k_init_eq(const uint8_t* __restrict__ cls, const real* __restrict__ rho,
-                          const real* __restrict__ u, real* __restrict__ f, int64_t N) {
+                          const real* __restrict__ u, real* __restrict__ f, int64_t N, int nx,
+                          int pitch) {
+    // storage index n (rows `pitch` apart; positions past nx in a row get 0);
+    // rho and u are dense, rows nx apart
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
-    const bool fluid = cls[n] == CLS_FLUID;
+    const int64_t row = n / pitch, x = n - row * pitch;
+    const int64_t nd = row * nx + x, Nd = N / pitch * nx;
+    const bool fluid = x < nx && cls[n] == CLS_FLUID;
     real uu[3] = {real(0), real(0), real(0)};
     if (fluid && u) {
 #pragma unroll
-        for (int d = 0; d < L::D; ++d) uu[d] = u[d * N + n];
+        for (int d = 0; d < L::D; ++d) uu[d] = u[d * Nd + nd];
     }
-    const real r = fluid ? rho[n] : real(0);
+    const real r = fluid ? rho[nd] : real(0);
 #pragma unroll
     for (int a = 0; a < L::Q; ++a) f[a * N + n] = fluid ? feq<L, real>(a, r, uu) : real(0);
 }
@@ -153,13 +158,14 @@ hipError_t launch_gather_wall(const int32_t* widx, const real* phi, const real* 
 
 template <typename real>
 hipError_t launch_init_eq(int lattice, const uint8_t* cls, const real* rho, const real* u,
-                          real* f, int64_t N, hipStream_t s) {
+                          real* f, int64_t N, hipStream_t s, int nx, int pitch) {
+    if (pitch < 1 || nx < 1 || nx > pitch || N % pitch) return hipErrorInvalidValue;
     if (lattice == 9)
         hipLaunchKernelGGL((k_init_eq<D2Q9, real>), dim3(nblk(N, 256)), dim3(256), 0, s, cls, rho,
-                           u, f, N);
+                           u, f, N, nx, pitch);
     else
         hipLaunchKernelGGL((k_init_eq<D3Q19, real>), dim3(nblk(N, 256)), dim3(256), 0, s, cls,
-                           rho, u, f, N);
+                           rho, u, f, N, nx, pitch);
     return hipGetLastError();
 }
 
@@ -206,9 +212,9 @@ hipError_t launch_diag_final(const double* part, int nparts, double* out, hipStr
 }
 
 template hipError_t launch_init_eq<float>(int, const uint8_t*, const float*, const float*, float*,
-                                          int64_t, hipStream_t);
+                                          int64_t, hipStream_t, int, int);
 template hipError_t launch_init_eq<double>(int, const uint8_t*, const double*, const double*,
-                                           double*, int64_t, hipStream_t);
+                                           double*, int64_t, hipStream_t, int, int);
 template hipError_t launch_scatter3<float>(const uint8_t*, const float*, float*, int, int, int,
                                            hipStream_t);
 template hipError_t launch_scatter3<double>(const uint8_t*, const double*, double*, int, int, int,

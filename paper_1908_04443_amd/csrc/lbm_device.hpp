@@ -109,6 +109,7 @@ struct Coef {
     real sig_e;     // 12 sigma / (tau_e - 1/2)  (3-D: 114 sigma / (tau_e - 1/2))
     real sig_eps;   // 12 sigma / (tau_eps - 1/2) (3-D: 0)
     real body[3];
+    int pitch = 0;  // D2Q9: nodes from one row to the next in the arrays (0: nx)
 };
 
 template <typename real>

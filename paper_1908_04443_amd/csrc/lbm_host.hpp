@@ -78,7 +78,10 @@ struct Carver {
 // one lattice of a multi-case context
 struct lbm_case {
     int nx = 0, ny = 0;
-    int64_t N = 0, n_wall_max = 0;
+    int pitch = 0;    // nodes from one row to the next in the case's arrays
+    int64_t N = 0;    // nx * ny lattice nodes
+    int64_t NP = 0;   // pitch * ny stored nodes
+    int64_t n_wall_max = 0;
     uint64_t f_off = 0, node_off = 0, wall_off = 0;
     lbm::Geometry geom;
     bool have_geom = false, have_fields = false;

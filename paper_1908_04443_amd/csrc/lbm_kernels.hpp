@@ -26,6 +26,7 @@ struct FieldOut {
 // indices: per-node arena; wetting parameters: per-wall arena).
 struct CaseDesc {
     int32_t nx, ny;
+    int32_t pitch, reserved;  // row pitch of the case's arrays (nodes), unused
     uint64_t f_off;
     uint64_t node_off;
     uint64_t wall_off;
@@ -162,9 +163,11 @@ hipError_t launch_adj_finish(const uint8_t* cls, const real* lam, const real* ex
                              uint32_t N, hipStream_t s);
 
 // auxiliary kernels
+// N storage nodes with rows `pitch` apart, of which the first nx of each row
+// are the lattice's (rho and u dense, rows nx apart); nx = pitch = 1: plain
 template <typename real>
 hipError_t launch_init_eq(int lattice, const uint8_t* cls, const real* rho, const real* u,
-                          real* f, int64_t N, hipStream_t s);
+                          real* f, int64_t N, hipStream_t s, int nx = 1, int pitch = 1);
 template <typename real>
 hipError_t launch_mask_solid(int Q, const uint8_t* cls, real* f, int64_t N, hipStream_t s);
 // D3Q19 pull form: post-stream f -> pull form (dst cleared first), and back

@@ -36,24 +36,29 @@
 namespace lbm {
 
 // The work of one TX x TY tile at (x0, y0) of an nx x ny lattice; shared by
-// the single-lattice kernel and the multi-case kernel.  part: index of this
-// tile's diagnostic partial; list_tile: its entry block in the wall lists.
+// the single-lattice kernel and the multi-case kernel.  The lattice's arrays
+// keep row y at y * pitch (pitch >= nx; the columns past nx are never read
+// or written); the outputs of the field mode are dense (row y at y * nx).
+// part: index of this tile's diagnostic partial; list_tile: its entry block
+// in the wall lists.
 template <typename real, int TX, int TY, int NT, int MODE, bool BUF, bool GFW>
 __device__ __forceinline__ void d2q9_tile(const Coef<real>& C, const Fields<real>& Fd,
-                                          const FieldOut<real>& Out, const int nx, const int ny,
-                                          const int x0, const int y0, const int part,
-                                          const int list_tile) {
+                                          const FieldOut<real>& Out, const int nx,
+                                          const int pitch, const int ny, const int x0,
+                                          const int y0, const int part, const int list_tile) {
     using L = D2Q9;
     constexpr int LX = TX + 4;
     constexpr int ROWS = NT / TX;
     constexpr int RPT = TY / ROWS;
     __shared__ TileLDS<real, TX, TY> S;
-    const uint32_t N = (uint32_t)nx * (uint32_t)ny;
+    const uint32_t N = (uint32_t)pitch * (uint32_t)ny;  // population plane stride
+    const uint32_t Nd = (uint32_t)nx * (uint32_t)ny;    // plane stride of the dense outputs
     const PopIO<real, BUF> io(Fd.fin, Fd.fout, N, 9);
     const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
     bool bad = false;
     real f[RPT][9];
-    d2q9_prologue<real, TX, TY, NT, BUF, GFW>(C, Fd, io, nx, ny, x0, y0, list_tile, S, f, bad);
+    d2q9_prologue<real, TX, TY, NT, BUF, GFW>(C, Fd, io, nx, pitch, ny, x0, y0, list_tile, S, f,
+                                              bad);
 
     double d_sum = 0.0;
     real d_umax = real(0), d_rmin = real(1e30), d_rmax = real(-1e30);
@@ -61,23 +66,33 @@ __device__ __forceinline__ void d2q9_tile(const Coef<real>& C, const Fields<real
     // the tile and its 1-node ring lie inside the lattice without wrapping
     const bool interior = x0 >= 1 && y0 >= 1 && x0 + TX + 1 <= nx && y0 + TY + 1 <= ny;
     // rows of every direction start on 128-byte boundaries
-    const bool lines = ((reinterpret_cast<uintptr_t>(Fd.fout) | ((uintptr_t)nx * sizeof(real)) |
+    const bool lines = ((reinterpret_cast<uintptr_t>(Fd.fout) | ((uintptr_t)pitch * sizeof(real)) |
                          ((uintptr_t)x0 * sizeof(real))) & 127) == 0;
 
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
         const int ly = ty + k * ROWS;
         const int gx = x0 + tx, gy = y0 + ly;
-        if (gx >= nx || gy >= ny) continue;  // ragged tile: not owned
+        if (gx >= nx || gy >= ny) {  // ragged tile: not owned
+            // a position of the row's padding (pitch > nx) is never read; it
+            // gets 0 so that the row's last cache line is written whole
+            if (MODE == MODE_STEP && gx < pitch && gy < ny) {
+                const uint32_t m = (uint32_t)gy * (uint32_t)pitch + (uint32_t)gx;
+#pragma unroll
+                for (int a = 0; a < 9; ++a) io.st(a, m, real(0));
+            }
+            continue;
+        }
         const int p = (ly + 2) * LX + tx + 2;
         const uint32_t n = S.row[ly + 2] + S.col[tx + 2];
+        const uint32_t od = (uint32_t)gy * (uint32_t)nx + (uint32_t)gx;  // dense output index
         const uint8_t c = S.cls[p];
         if (c != CLS_FLUID) {
             if (MODE == MODE_FIELDS) {
-                if (Out.rho) Out.rho[n] = (c == CLS_WALL) ? S.rho[p] : real(0);
+                if (Out.rho) Out.rho[od] = (c == CLS_WALL) ? S.rho[p] : real(0);
                 if (Out.u) {
-                    Out.u[n] = real(0);
-                    Out.u[(size_t)N + n] = real(0);
+                    Out.u[od] = real(0);
+                    Out.u[(size_t)Nd + od] = real(0);
                 }
             }
             continue;
@@ -92,10 +107,10 @@ __device__ __forceinline__ void d2q9_tile(const Coef<real>& C, const Fields<real
             const real jy = f[k][2] - f[k][4] + f[k][5] + f[k][6] - f[k][7] - f[k][8];
             const real ux = (jx + real(0.5) * F[0]) / rho;
             const real uy = (jy + real(0.5) * F[1]) / rho;
-            if (Out.rho) Out.rho[n] = rho;
+            if (Out.rho) Out.rho[od] = rho;
             if (Out.u) {
-                Out.u[n] = ux;
-                Out.u[(size_t)N + n] = uy;
+                Out.u[od] = ux;
+                Out.u[(size_t)Nd + od] = uy;
             }
             const real um = sqrt(ux * ux + uy * uy);
             // mass: the node's populations summed in FP64 (in FP32 the
@@ -116,7 +131,7 @@ __device__ __forceinline__ void d2q9_tile(const Coef<real>& C, const Fields<real
         collide<L, real>(C, f[k], rho, F, Fm, psi_c, fs, u);
         // push streaming with halfway bounce-back
         if (interior) {
-            // no neighbour wraps: the target is n + ex + ey nx
+            // no neighbour wraps: the target is n + ex + ey pitch
             // With rows on 128-byte boundaries, the directions with ex = 0
             // fill whole cache lines of this tile (the rest population never
             // leaves its node; the y neighbours of a row segment lie in one
@@ -129,9 +144,9 @@ __device__ __forceinline__ void d2q9_tile(const Coef<real>& C, const Fields<real
                     const int q = p + L::ex[a] + L::ey[a] * LX;
                     if (NT_OK && L::ex[a] == 0)
                         io.template st_push<ST_NT>(S.cls[q] == CLS_FLUID, a, L::opp[a],
-                                                   L::ey[a] * nx, n, fs[a]);
+                                                   L::ey[a] * pitch, n, fs[a]);
                     else
-                        io.st_push(S.cls[q] == CLS_FLUID, a, L::opp[a], L::ex[a] + L::ey[a] * nx,
+                        io.st_push(S.cls[q] == CLS_FLUID, a, L::opp[a], L::ex[a] + L::ey[a] * pitch,
                                    n, fs[a]);
                 }
             };
@@ -178,7 +193,8 @@ __global__ __launch_bounds__(NT, OCC) void k_step_d2q9(Coef<real> C, Fields<real
         bx = bid % gxb;
         by = bid / gxb;
     }
-    d2q9_tile<real, TX, TY, NT, MODE, BUF, GFW>(C, Fd, Out, C.nx, C.ny, bx * TX, by * TY, bid,
+    d2q9_tile<real, TX, TY, NT, MODE, BUF, GFW>(C, Fd, Out, C.nx, C.pitch > 0 ? C.pitch : C.nx,
+                                                C.ny, bx * TX, by * TY, bid,
                                                 by * gxb + bx);
 }
 
@@ -215,8 +231,8 @@ __global__ __launch_bounds__(NT) void k_step_d2q9_batch(Coef<real> C, BatchArgs<
     Fd.tw_stride = B.tw_stride;
     Fd.tw_code = B.tw_code;
     FieldOut<real> none{nullptr, nullptr, nullptr};
-    d2q9_tile<real, TX, TY, NT, MODE_STEP, BUF, false>(C, Fd, none, cd.nx, cd.ny, t.x0, t.y0, bid,
-                                                    bid);
+    d2q9_tile<real, TX, TY, NT, MODE_STEP, BUF, false>(C, Fd, none, cd.nx, cd.pitch, cd.ny, t.x0,
+                                                    t.y0, bid, bid);
 }
 
 // ----------------------------------------------------------------- launch
@@ -272,7 +288,7 @@ static void launch_v(const Coef<real>& C, const Fields<real>& F, const FieldOut<
     constexpr Shape2D sh = Variants2D<real>::shape[V];
     dim3 grid((C.nx + sh.TX - 1) / sh.TX, (C.ny + sh.TY - 1) / sh.TY);
     if constexpr (sh.vec && std::is_same<real, float>::value && MODE == MODE_STEP && BUF) {
-        if (C.nx % 4 == 0) {
+        if (C.nx % 4 == 0 && (C.pitch == 0 || C.pitch == C.nx)) {
             hipLaunchKernelGGL((k_step_d2q9_vec<sh.TX, sh.TY, sh.NT, sh.xcd, sh.occ, GFW>), grid,
                                dim3(sh.NT), 0, s, C, F);
             return;

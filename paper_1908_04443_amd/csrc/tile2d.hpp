@@ -19,7 +19,7 @@ struct TileLDS {
     real rho[LX * LY];
     real psi[LX * LY];
     uint32_t col[LX];  // wrapped x of each halo column
-    uint32_t row[LY];  // wrapped y * nx of each halo row
+    uint32_t row[LY];  // wrapped y * pitch of each halo row
     int wl_count;      // wall-list length of the tile
 };
 
@@ -225,7 +225,8 @@ __device__ __forceinline__ void d2q9_psi_phase(const Coef<real>& C, const Fields
 template <typename real, int TX, int TY, int NT, bool BUF, bool GFW = false>
 __device__ __forceinline__ void d2q9_prologue(const Coef<real>& C, const Fields<real>& Fd,
                                               const PopIO<real, BUF>& io, const int nx,
-                                              const int ny, const int x0, const int y0,
+                                              const int pitch, const int ny, const int x0,
+                                              const int y0,
                                               const int list_tile, TileLDS<real, TX, TY>& S,
                                               real (&f)[TY / (NT / TX)][9], bool& bad) {
     constexpr int LX = TX + 4, LY = TY + 4;
@@ -243,12 +244,13 @@ __device__ __forceinline__ void d2q9_prologue(const Coef<real>& C, const Fields<
     // lie wholly inside solid regions and saves a dependent round trip.
     const bool inner2 = x0 >= 2 && y0 >= 2 && x0 + TX + 2 <= nx && y0 + TY + 2 <= ny;
     auto node = [&](int lx, int ly) -> uint32_t {
-        if (inner2) return (uint32_t)(y0 - 2 + ly) * (uint32_t)nx + (uint32_t)(x0 - 2 + lx);
-        return (uint32_t)wrapi(y0 - 2 + ly, ny) * (uint32_t)nx + (uint32_t)wrapi(x0 - 2 + lx, nx);
+        if (inner2) return (uint32_t)(y0 - 2 + ly) * (uint32_t)pitch + (uint32_t)(x0 - 2 + lx);
+        return (uint32_t)wrapi(y0 - 2 + ly, ny) * (uint32_t)pitch +
+               (uint32_t)wrapi(x0 - 2 + lx, nx);
     };
     for (int i = tid; i < LX + LY; i += NT) {
         if (i < LX) S.col[i] = (uint32_t)wrapi(x0 - 2 + i, nx);
-        else S.row[i - LX] = (uint32_t)wrapi(y0 - 2 + (i - LX), ny) * (uint32_t)nx;
+        else S.row[i - LX] = (uint32_t)wrapi(y0 - 2 + (i - LX), ny) * (uint32_t)pitch;
     }
 
     // Per-tile wall list (improved virtual density, geometric formulation):

@@ -84,6 +84,7 @@ def lib():
             "lbm_set_variant": (C.c_int, [vp, C.c_int32]),
             "lbm_get_variant": (C.c_int, [vp, C.POINTER(C.c_int32)]),
             "lbm_autotune": (C.c_int, [vp, i64, vp, C.POINTER(C.c_int32), dp]),
+            "lbm_autotune_save_bytes": (C.c_size_t, [vp]),
             "lbm_set_graph_steps": (C.c_int, [vp, i64]),
             "lbm_adjoint_workspace_bytes": (C.c_size_t, [vp, i64]),
             "lbm_step_ckpt": (C.c_int, [vp, i64, i64, vp]),
@@ -255,6 +256,10 @@ def lbm_get_variant(ctx):
     v = C.c_int32()
     _check(lib().lbm_get_variant(ctx, C.byref(v)), "lbm_get_variant")
     return v.value
+
+
+def lbm_autotune_save_bytes(ctx):
+    return lib().lbm_autotune_save_bytes(ctx)
 
 
 def lbm_autotune(ctx, steps, save=None, nvariants=None):
@@ -465,7 +470,7 @@ class Solver:
     def autotune(self, steps=20, report=False):
         """Pick the fastest step-kernel variant on this problem; the state is
         saved and restored around the trials."""
-        save = torch.empty(self.Q * self.N, dtype=self.dtype, device=self.device)
+        save = torch.empty(lbm_autotune_save_bytes(self.ctx), dtype=torch.uint8, device=self.device)
         nv = lbm_variant_count(self.p.lattice, self.p.precision) if report else None
         best, ms = lbm_autotune(self.ctx, steps, save, nv)
         torch.cuda.synchronize(self.device)
@@ -623,8 +628,7 @@ class BatchSolver:
         return lbm_get_diagnostics_case(self.ctx, i)
 
     def autotune(self, steps=10, report=False):
-        nb = sum(9 * a * b for a, b in self.sizes) + 64 * len(self.sizes)
-        save = torch.empty(nb, dtype=self.dtype, device=self.device)
+        save = torch.empty(lbm_autotune_save_bytes(self.ctx), dtype=torch.uint8, device=self.device)
         nv = lbm_variant_count(9, self.p.precision) if report else None
         best, ms = lbm_autotune(self.ctx, steps, save, nv)
         torch.cuda.synchronize(self.device)
