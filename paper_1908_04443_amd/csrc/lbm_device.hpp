@@ -239,6 +239,20 @@ struct PopIO {
             fout[stream ? (int64_t)a * N + n + delta : (int64_t)b * N + n] = v;
         }
     }
+    // the same with the streaming target given as a node (m), where it is
+    // not at one offset across the wavefront (a tile whose neighbours wrap)
+    template <int AUX = 0>
+    __device__ __forceinline__ void st_sel(bool stream, int a, int b, uint32_t m, uint32_t n,
+                                           real v) const {
+        const int lo = a < b ? a : b;
+        if constexpr (BUF) {
+            const uint32_t e = stream ? (uint32_t)(a - lo) * N + m : (uint32_t)(b - lo) * N + n;
+            buf_st<real, AUX>(v, rout, e * (uint32_t)sizeof(real),
+                              (uint32_t)lo * N * (uint32_t)sizeof(real));
+        } else {
+            fout[stream ? (int64_t)a * N + m : (int64_t)b * N + n] = v;
+        }
+    }
     // store to node n + delta of direction a, delta uniform across the
     // wavefront: the shift goes into the scalar offset, so every direction
     // shares the per-lane offset of n.  Needs a * N + delta >= 0.

@@ -40,8 +40,10 @@ namespace lbm {
 // keep row y at y * pitch (pitch >= nx; the columns past nx are never read
 // or written); the outputs of the field mode are dense (row y at y * nx).
 // part: index of this tile's diagnostic partial; list_tile: its entry block
-// in the wall lists.
-template <typename real, int TX, int TY, int NT, int MODE, bool BUF, bool GFW>
+// in the wall lists.  WNT: tiles whose ring wraps also store the directions
+// with ex = 0 non-temporally on line-aligned rows (measured: the 96-case
+// launch 1.7 % faster, where most tiles wrap; the 2048^2 step 0.5 % slower).
+template <typename real, int TX, int TY, int NT, int MODE, bool BUF, bool GFW, bool WNT = false>
 __device__ __forceinline__ void d2q9_tile(const Coef<real>& C, const Fields<real>& Fd,
                                           const FieldOut<real>& Out, const int nx,
                                           const int pitch, const int ny, const int x0,
@@ -153,16 +155,28 @@ __device__ __forceinline__ void d2q9_tile(const Coef<real>& C, const Fields<real
             if (lines) push(std::true_type{});
             else push(std::false_type{});
         } else {
+            // a tile whose ring wraps: the neighbours' rows and columns come
+            // from the tile's tables, and each direction is one store (to the
+            // neighbour, or back to this node's opposite slot).  A wrap only
+            // changes which row the directions with ex = 0 land in, so on
+            // line-aligned rows they still fill whole lines of this tile.
+            const uint32_t col[3] = {S.col[tx + 1], S.col[tx + 2], S.col[tx + 3]};
+            const uint32_t row[3] = {S.row[ly + 1], S.row[ly + 2], S.row[ly + 3]};
+            auto push = [&](auto whole) {
+                constexpr bool NT_OK = decltype(whole)::value;
 #pragma unroll
-            for (int a = 0; a < 9; ++a) {
-                const int q = p + L::ex[a] + L::ey[a] * LX;
-                if (S.cls[q] == CLS_FLUID) {
-                    const uint32_t m = S.row[ly + 2 + L::ey[a]] + S.col[tx + 2 + L::ex[a]];
-                    io.st(a, m, fs[a]);
-                } else {
-                    io.st(L::opp[a], n, fs[a]);
+                for (int a = 0; a < 9; ++a) {
+                    const int q = p + L::ex[a] + L::ey[a] * LX;
+                    const uint32_t m = row[1 + L::ey[a]] + col[1 + L::ex[a]];
+                    if (NT_OK && L::ex[a] == 0)
+                        io.template st_sel<ST_NT>(S.cls[q] == CLS_FLUID, a, L::opp[a], m, n,
+                                                  fs[a]);
+                    else
+                        io.st_sel(S.cls[q] == CLS_FLUID, a, L::opp[a], m, n, fs[a]);
                 }
-            }
+            };
+            if (WNT && lines) push(std::true_type{});
+            else push(std::false_type{});
         }
     }
 
@@ -231,8 +245,8 @@ __global__ __launch_bounds__(NT) void k_step_d2q9_batch(Coef<real> C, BatchArgs<
     Fd.tw_stride = B.tw_stride;
     Fd.tw_code = B.tw_code;
     FieldOut<real> none{nullptr, nullptr, nullptr};
-    d2q9_tile<real, TX, TY, NT, MODE_STEP, BUF, false>(C, Fd, none, cd.nx, cd.pitch, cd.ny, t.x0,
-                                                    t.y0, bid, bid);
+    d2q9_tile<real, TX, TY, NT, MODE_STEP, BUF, false, true>(C, Fd, none, cd.nx, cd.pitch, cd.ny,
+                                                          t.x0, t.y0, bid, bid);
 }
 
 // ----------------------------------------------------------------- launch
