@@ -78,6 +78,30 @@ def test_batch_equals_single_bitwise(oracle_mod, gpu_lib, precision):
             assert torch.equal(a[key], c[key]), (i, key)
 
 
+@pytest.mark.parametrize("precision", [4, 8])
+def test_batch_initial_velocity_equals_single(oracle_mod, gpu_lib, precision):
+    """Cases whose widths are not whole cache lines (so their rows are padded
+    inside the multi-case context) started from rho and a nonzero u: every
+    case bitwise equal to the same case started and run alone."""
+    import torch
+    setups = [Setup(oracle_mod, c) for c in _case_dicts(precision)]
+    rng = np.random.default_rng(77)
+    us = [0.02 * rng.standard_normal((2, s.case["ny"] * s.case["nx"])) for s in setups]
+    b = _batch(gpu_lib, setups, 0)
+    for i, s in enumerate(setups):
+        b.set_fields(i, s.rho0.ravel(), us[i])
+    b.step(60)
+    for i, s in enumerate(setups):
+        one = _single(gpu_lib, s, 0)
+        one.set_fields(s.rho0.ravel(), us[i])
+        one.step(60)
+        a = b.get_fields(i, f=True)
+        c = one.get_fields(f=True)
+        torch.cuda.synchronize()
+        for key in ("rho", "u", "f"):
+            assert torch.equal(a[key], c[key]), (i, key)
+
+
 @pytest.mark.parametrize("variant", range(4))  # the FP64 tile shapes
 def test_batch_every_tile_shape_vs_oracle(oracle_mod, gpu_lib, variant):
     setups = [Setup(oracle_mod, c) for c in _case_dicts(8)]

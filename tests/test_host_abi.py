@@ -122,6 +122,18 @@ def test_null_context_calls(L):
     assert lib.lbm_get_fields(None, None, None, None) == L.LBM_EINVAL
     assert lib.lbm_set_wetting(None, 0, 0.0, None, None, 1.0, 0.0) == L.LBM_EINVAL
     assert lib.lbm_destroy(None) == 0
+    assert lib.lbm_autotune_save_bytes(None) == 0
+
+
+def test_batch_rows_take_whole_lines(L):
+    """A multi-case context stores each case's rows a whole number of
+    128-byte lines apart: a 33-wide FP32 case needs the room of a 64-wide
+    one (every tile shape covers both with one tile column), a 65-wide one
+    more."""
+    p = _good(L, nx=1, ny=1)
+    ws = lambda nx: L.lbm_batch_workspace_bytes(p, [nx, 40], [50, 50], [10, 10])
+    assert ws(33) == ws(64) > 0
+    assert ws(65) > ws(64)
 
 
 def test_eos_helpers_match_oracle(L, oracle_mod):
