@@ -306,8 +306,10 @@ int lbm_set_graph_steps(lbm_ctx* ctx, int64_t steps);
  * lbm_set_wetting (scheme and uniform values for all cases),
  * lbm_set_graph_steps, lbm_set_variant, lbm_autotune and
  * lbm_get_diagnostics (totals over the cases) accept such a context; the
- * single-lattice geometry/fields calls return LBM_EINVAL for it.  Each
- * case's populations must stay below 4 GiB. */
+ * single-lattice geometry/fields calls return LBM_EINVAL for it.  Inside
+ * the context each case's rows start on 128-byte boundaries (the width is
+ * padded to whole lines); the per-case calls take and give dense arrays.
+ * Each case's populations, rows padded, must stay below 4 GiB. */
 size_t lbm_batch_workspace_bytes(const lbm_params* p, int32_t ncases, const int32_t* nx,
                                  const int32_t* ny, const int64_t* n_wall_max);
 int lbm_create_batch(const lbm_params* p, int32_t ncases, const int32_t* nx, const int32_t* ny,
