@@ -37,8 +37,9 @@ namespace lbm {
 
 // The work of one TX x TY tile at (x0, y0) of an nx x ny lattice; shared by
 // the single-lattice kernel and the multi-case kernel.  The lattice's arrays
-// keep row y at y * pitch (pitch >= nx; the columns past nx are never read
-// or written); the outputs of the field mode are dense (row y at y * nx).
+// keep row y at y * pitch (pitch >= nx; the columns past nx are never read,
+// and a step writes 0 into those its tiles cover); the outputs of the field
+// mode are dense (row y at y * nx).
 // part: index of this tile's diagnostic partial; list_tile: its entry block
 // in the wall lists.  WNT: tiles whose ring wraps also store the directions
 // with ex = 0 non-temporally on line-aligned rows (measured: the 96-case
