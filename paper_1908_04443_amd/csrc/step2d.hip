@@ -41,10 +41,13 @@ namespace lbm {
 // and a step writes 0 into those its tiles cover); the outputs of the field
 // mode are dense (row y at y * nx).
 // part: index of this tile's diagnostic partial; list_tile: its entry block
-// in the wall lists.  WNT: tiles whose ring wraps also store the directions
-// with ex = 0 non-temporally on line-aligned rows (measured: the 96-case
-// launch 1.7 % faster, where most tiles wrap; the 2048^2 step 0.5 % slower).
-template <typename real, int TX, int TY, int NT, int MODE, bool BUF, bool GFW, bool WNT = false>
+// in the wall lists.  MC: the multi-case kernel's two choices, each measured
+// faster on the 96 uneven cases (where most tiles wrap) and slower on the
+// 2048^2 lattice: tiles whose ring wraps also store the directions with
+// ex = 0 non-temporally on line-aligned rows (1.7 % faster there, 0.5 %
+// slower here), and populations are loaded for fluid nodes only (2.0 %
+// faster there, 1.3 % slower here).
+template <typename real, int TX, int TY, int NT, int MODE, bool BUF, bool GFW, bool MC = false>
 __device__ __forceinline__ void d2q9_tile(const Coef<real>& C, const Fields<real>& Fd,
                                           const FieldOut<real>& Out, const int nx,
                                           const int pitch, const int ny, const int x0,
@@ -60,8 +63,8 @@ __device__ __forceinline__ void d2q9_tile(const Coef<real>& C, const Fields<real
     const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
     bool bad = false;
     real f[RPT][9];
-    d2q9_prologue<real, TX, TY, NT, BUF, GFW>(C, Fd, io, nx, pitch, ny, x0, y0, list_tile, S, f,
-                                              bad);
+    d2q9_prologue<real, TX, TY, NT, BUF, GFW, MC>(C, Fd, io, nx, pitch, ny, x0, y0, list_tile, S,
+                                                  f, bad);
 
     double d_sum = 0.0;
     real d_umax = real(0), d_rmin = real(1e30), d_rmax = real(-1e30);
@@ -176,7 +179,7 @@ __device__ __forceinline__ void d2q9_tile(const Coef<real>& C, const Fields<real
                         io.st_sel(S.cls[q] == CLS_FLUID, a, L::opp[a], m, n, fs[a]);
                 }
             };
-            if (WNT && lines) push(std::true_type{});
+            if (MC && lines) push(std::true_type{});
             else push(std::false_type{});
         }
     }

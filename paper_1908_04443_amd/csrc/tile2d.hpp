@@ -221,8 +221,11 @@ __device__ __forceinline__ void d2q9_psi_phase(const Coef<real>& C, const Fields
 }
 
 // GFW: the geometric formulation is compiled in (a separate instantiation,
-// so that the other schemes keep its registers out of their kernels)
-template <typename real, int TX, int TY, int NT, bool BUF, bool GFW = false>
+// so that the other schemes keep its registers out of their kernels).
+// FLO: populations are loaded for fluid nodes only, once their classes have
+// arrived (non-fluid slots are never used).  That saves the lines inside
+// solids at the cost of a second dependent round trip per tile.
+template <typename real, int TX, int TY, int NT, bool BUF, bool GFW = false, bool FLO = false>
 __device__ __forceinline__ void d2q9_prologue(const Coef<real>& C, const Fields<real>& Fd,
                                               const PopIO<real, BUF>& io, const int nx,
                                               const int pitch, const int ny, const int x0,
@@ -261,13 +264,21 @@ __device__ __forceinline__ void d2q9_prologue(const Coef<real>& C, const Fields<
 
     // owned tile nodes: populations into registers, density into LDS
     uint8_t oc[RPT];
+    uint32_t on[RPT];
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
         const int ly = ty + k * ROWS;
-        const uint32_t n = node(tx + 2, ly + 2);
-        oc[k] = Fd.cls[n];
+        on[k] = node(tx + 2, ly + 2);
+        oc[k] = Fd.cls[on[k]];
+    }
 #pragma unroll
-        for (int a = 0; a < 9; ++a) f[k][a] = io.ld(a, n);
+    for (int k = 0; k < RPT; ++k) {
+#pragma unroll
+        for (int a = 0; a < 9; ++a) f[k][a] = real(0);
+        if (!FLO || oc[k] == CLS_FLUID) {
+#pragma unroll
+            for (int a = 0; a < 9; ++a) f[k][a] = io.ld(a, on[k]);
+        }
     }
     // halo ring: density only
     constexpr int JR = (RING + NT - 1) / NT;
@@ -283,10 +294,12 @@ __device__ __forceinline__ void d2q9_prologue(const Coef<real>& C, const Fields<
             ring_pos<TX, TY>(j, lx, ly);
             const uint32_t n = node(lx, ly);
             rc[jj] = Fd.cls[n];
-            real r = io.ld(0, n);
+            if (!FLO || rc[jj] == CLS_FLUID) {
+                real r = io.ld(0, n);
 #pragma unroll
-            for (int a = 1; a < 9; ++a) r += io.ld(a, n);
-            rr[jj] = r;
+                for (int a = 1; a < 9; ++a) r += io.ld(a, n);
+                rr[jj] = r;
+            }
         }
     }
 #pragma unroll
