@@ -334,12 +334,20 @@ static int upload_wall_lists(lbm_ctx* c, const std::vector<ListTile>& tiles, int
     auto node = [&](const ListTile& t, int lx, int ly) {
         return (int64_t)wrap(t.y0 - 2 + ly, t.ny) * t.nx + wrap(t.x0 - 2 + lx, t.nx);
     };
+    // in a ragged tile psi is needed up to one node past the lattice's last
+    // column or row (the force of its owned nodes), so walls further out
+    // carry no entry: none of them forms a virtual density next to the cells
+    // the multi-case step leaves empty (two nodes past and beyond)
+    auto listed = [&](const ListTile& t, int lx, int ly) {
+        return t.x0 - 2 + lx <= t.nx && t.y0 - 2 + ly <= t.ny &&
+               t.g->cls[node(t, lx, ly)] == CLS_WALL;
+    };
     std::vector<int32_t> cnt(nt, 0);
     int maxc = 0;
     for (int64_t i = 0; i < nt; ++i) {
         int k = 0;
         for (int ly = 1; ly <= TY + 2; ++ly)
-            for (int lx = 1; lx <= TX + 2; ++lx) k += tiles[i].g->cls[node(tiles[i], lx, ly)] == CLS_WALL;
+            for (int lx = 1; lx <= TX + 2; ++lx) k += listed(tiles[i], lx, ly);
         cnt[i] = k;
         maxc = k > maxc ? k : maxc;
     }
@@ -356,8 +364,8 @@ static int upload_wall_lists(lbm_ctx* c, const std::vector<ListTile>& tiles, int
         int k = 0;
         for (int ly = 1; ly <= TY + 2; ++ly)
             for (int lx = 1; lx <= TX + 2; ++lx) {
+                if (!listed(tiles[i], lx, ly)) continue;
                 const int64_t n = node(tiles[i], lx, ly);
-                if (tiles[i].g->cls[n] != CLS_WALL) continue;
                 pack[e0 + k] = hi | (ly * LX + lx);
                 widx[e0 + k] = (int32_t)(tiles[i].woff + tiles[i].g->widx[n]);
                 ++k;

@@ -269,7 +269,14 @@ __device__ __forceinline__ void d2q9_prologue(const Coef<real>& C, const Fields<
     for (int k = 0; k < RPT; ++k) {
         const int ly = ty + k * ROWS;
         on[k] = node(tx + 2, ly + 2);
-        oc[k] = Fd.cls[on[k]];
+        // FLO with a wall list: a position more than two nodes past the
+        // lattice's last column or row (ragged tiles) is nobody's neighbour
+        // and stays an empty solid cell.  (psi is needed up to one node past
+        // the owned nodes; the list holds no wall beyond that, so no virtual
+        // density is formed next to an empty cell.)
+        oc[k] = (FLO && we.on && (x0 + tx >= nx + 2 || y0 + ly >= ny + 2))
+                    ? (uint8_t)CLS_SOLID
+                    : Fd.cls[on[k]];
     }
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
@@ -293,7 +300,9 @@ __device__ __forceinline__ void d2q9_prologue(const Coef<real>& C, const Fields<
             int lx, ly;
             ring_pos<TX, TY>(j, lx, ly);
             const uint32_t n = node(lx, ly);
-            rc[jj] = Fd.cls[n];
+            rc[jj] = (FLO && we.on && (x0 - 2 + lx >= nx + 2 || y0 - 2 + ly >= ny + 2))
+                         ? (uint8_t)CLS_SOLID
+                         : Fd.cls[n];
             if (!FLO || rc[jj] == CLS_FLUID) {
                 real r = io.ld(0, n);
 #pragma unroll

@@ -102,6 +102,45 @@ def test_batch_initial_velocity_equals_single(oracle_mod, gpu_lib, precision):
             assert torch.equal(a[key], c[key]), (i, key)
 
 
+def _seam_cases(precision):
+    """Widths that leave ragged tiles, with solid slabs on the periodic seam:
+    columns 0-1 over most rows and rows 0-1 over some columns, so that a wall
+    at x = 1 (y = 1) has fluid only at x = 2 (y = 2), i.e. two nodes past the
+    last column (row) as a ragged tile sees it."""
+    out = []
+    for k, (nx, ny) in enumerate([(70, 50), (200, 40), (33, 45)]):
+        m = np.zeros((ny, nx), np.uint8)
+        m[4:ny - 4, 0:2] = 1
+        m[0:2, 6:nx // 2] = 1
+        out.append(dict(nx=nx, ny=ny, geometry=("mask", m),
+                        init=("droplet", (nx // 2 + 4, ny // 2), min(nx, ny) // 5), scheme="ivd",
+                        phi=1.1, drho=0.0, noise=1e-6, seed=40 + k, precision=precision))
+    return out
+
+
+@pytest.mark.parametrize("precision", [4, 8])
+def test_batch_walls_on_the_seam(oracle_mod, gpu_lib, precision):
+    """Walls next to the nodes a ragged tile of the multi-case step leaves
+    empty: no domain error, every case bitwise equal to the same case run
+    alone, and (FP64) the oracle to 1e-12."""
+    import torch
+    setups = [Setup(oracle_mod, c) for c in _seam_cases(precision)]
+    b = _batch(gpu_lib, setups, 40)
+    rc, _ = b.diagnostics()
+    assert rc == 0
+    for i, s in enumerate(setups):
+        one = _single(gpu_lib, s, 40)
+        a = b.get_fields(i, f=True)
+        c = one.get_fields(f=True)
+        torch.cuda.synchronize()
+        for key in ("rho", "u", "f"):
+            assert torch.equal(a[key], c[key]), (i, key)
+        if precision == 8:
+            f = oracle_mod.run(s.op, s.solid, s.f0, 40, s.phi, s.drho)
+            rho_o, _, _ = oracle_mod.fields(s.op, s.solid, f, s.phi, s.drho)
+            assert np.abs(a["rho"].cpu().numpy() - rho_o).max() <= 1e-12, i
+
+
 @pytest.mark.parametrize("variant", range(4))  # the FP64 tile shapes
 def test_batch_every_tile_shape_vs_oracle(oracle_mod, gpu_lib, variant):
     setups = [Setup(oracle_mod, c) for c in _case_dicts(8)]
