@@ -155,6 +155,27 @@ def test_batch_every_tile_shape_vs_oracle(oracle_mod, gpu_lib, variant):
 
 
 @pytest.mark.parametrize("variant", range(16))  # the FP32 tile shapes
+def test_batch_fp32_tile_shapes_equal_single(oracle_mod, gpu_lib, variant):
+    """The multi-case kernel's own paths (fluid-only loads, empty cells past a
+    ragged case edge, non-temporal stores in wrapped tiles) on every FP32 tile
+    shape: each case bitwise equal to the same case run alone on the default
+    tile."""
+    import torch
+    from paper_1908_04443_amd import lbm
+    if variant >= lbm.lbm_variant_count(9, 4) - 3:  # the y-sweep variants are single-lattice
+        pytest.skip("no such tile shape")
+    setups = [Setup(oracle_mod, c) for c in _case_dicts(4)]
+    b = _batch(gpu_lib, setups, 60, variant=variant)
+    for i, s in enumerate(setups):
+        one = _single(gpu_lib, s, 60)
+        a = b.get_fields(i, f=True)
+        c = one.get_fields(f=True)
+        torch.cuda.synchronize()
+        for key in ("rho", "u", "f"):
+            assert torch.equal(a[key], c[key]), (variant, i, key)
+
+
+@pytest.mark.parametrize("variant", range(16))  # the FP32 tile shapes
 def test_batch_fp32_tile_shapes_vs_oracle(oracle_mod, gpu_lib, variant):
     """Every FP32 tile shape of the multi-case launch (the 16-byte variants'
     shapes run the scalar multi-case tile) against the FP64 oracle, FP32
